@@ -1,0 +1,313 @@
+/*
+ * ctaug.h -- C ABI of the MI355X (gfx950) CT data-augmentation library.
+ *
+ * The library implements the GPU augmentation path of Rister et al., "CT organ
+ * segmentation using GPU data augmentation, unsupervised labels and IOU loss"
+ * (arXiv:1811.11226), Sec. "GPU-accelerated data augmentation": a 3-D CT
+ * volume is resampled through a random affine coordinate map x' = A x + b
+ * with trilinear interpolation, the label volume is warped through the same
+ * map by nearest-neighbour lookup, and photometric transforms and generated
+ * Gaussian noise are applied, all in one pass per output voxel.  Additions
+ * beyond the paper: gain/offset/gamma, a dense or cubic-B-spline displacement
+ * added to the affine map, adjoints (image, affine parameters, displacement,
+ * control grid), and a batched launch over volumes of uneven sizes.
+ *
+ * Conventions shared by every call
+ * ---------------------------------
+ *  - Volumes are dense C-order arrays [X][Y][Z] (z fastest).  Output voxel
+ *    p = (x, y, z) has linear index v = (x*Y + y)*Z + z.
+ *  - Data pointers named "device" are HIP device pointers owned by the caller;
+ *    the library never frees or retains them.  Small parameter blocks (the
+ *    3x4 matrix, photometric parameters, dimension triples) are host pointers
+ *    read before the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every compute call is asynchronous and stream-ordered; none synchronises.
+ *  - Arguments are validated before anything is enqueued.  On any error the
+ *    call returns a nonzero ctaug_status and leaves every output untouched.
+ *    No exception crosses the ABI and the library never prints.
+ *  - The only calls that allocate device or pinned memory are
+ *    ctaug_batch_plan_create (owned by the plan, freed by
+ *    ctaug_batch_plan_destroy); compute calls take caller workspace.
+ *  - Empty volumes (a zero dimension) are valid and make a call a no-op.
+ *  - The sampling coordinate of output voxel p is, per axis i,
+ *        q_i = fmaf(A_i2, z, fmaf(A_i1, y, fmaf(A_i0, x, b_i)))
+ *    in FP32 (plus u_i(p) as one FP32 addition when a displacement is given),
+ *    so that results are reproducible bit for bit across launch shapes.
+ *    Integer coordinates are voxel centres.  M = [A|b] maps OUTPUT voxel
+ *    coordinates to INPUT voxel coordinates (I_out(p) = I_in(A p + b)).
+ */
+#ifndef CTAUG_H
+#define CTAUG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTAUG_OK = 0,
+    CTAUG_EINVAL = 1,      /* null pointer, non-finite parameter, bad flag, ... */
+    CTAUG_EDTYPE = 2,      /* unsupported dtype for this argument */
+    CTAUG_ESHAPE = 3,      /* negative / inconsistent / too large dimensions */
+    CTAUG_EWORKSPACE = 4,  /* workspace missing or smaller than required */
+    CTAUG_EHIP = 5,        /* a HIP runtime call or kernel launch failed */
+    CTAUG_ENODEV = 6       /* no usable gfx950 device */
+} ctaug_status;
+
+typedef enum {
+    CTAUG_F32 = 0,         /* float32 */
+    CTAUG_I16 = 1,         /* int16 (e.g. 12-bit CT in HU) */
+    CTAUG_I8 = 2           /* int8 labels */
+} ctaug_dtype;
+
+/* A dense volume.  data: device pointer; dim: X, Y, Z (each >= 0).
+ * Element counts up to 2^31 - 1 per volume are supported. */
+typedef struct {
+    void *data;
+    int32_t dtype;         /* ctaug_dtype */
+    int32_t reserved;      /* must be 0 */
+    int64_t dim[3];
+} ctaug_vol;
+
+#define CTAUG_PHOTO_WINDOW 1u   /* apply window [win_lo, win_hi] -> [0,1] and gamma */
+
+/* Photometric parameters of one volume (Sec. "GPU-accelerated data
+ * augmentation", noise and window paragraphs; gain, offset and gamma are
+ * additions).  For each output voxel with interpolated value V:
+ *     v = gain * V + offset
+ *     v = v + sigma * n(v_index)          n ~ N(0,1), see ctaug_noise
+ *     if WINDOW: t = min(max((v - win_lo) / (win_hi - win_lo), 0), 1)
+ *                out = t^gamma  (0^gamma = 0)
+ *     else       out = v  (Hounsfield units)
+ * Requirements: all values finite; sigma >= 0; gamma > 0; win_hi > win_lo
+ * when WINDOW is set.  sigma == 0 adds no noise (the result is exactly the
+ * noiseless value). */
+typedef struct {
+    float gain, offset, sigma, win_lo, win_hi, gamma;
+    uint32_t flags;        /* CTAUG_PHOTO_* bits */
+    uint32_t volume_id;    /* Philox counter word 2 */
+    uint64_t seed;         /* Philox key */
+} ctaug_photo;
+
+/* Raw draws of the random affine transform (Sec. "GPU-accelerated data
+ * augmentation", first paragraph and footnote; crop from Sec. "Pre- and
+ * post-processing").  All FP64. */
+typedef struct {
+    double rot[3];         /* rotation angles about x, y, z (radians) */
+    double scale[3];       /* scale factors along x, y, z */
+    double shear[3];       /* h_xy, h_xz, h_yz of [[1,h_xy,h_xz],[0,1,h_yz],[0,0,1]] */
+    double reflect[3];     /* 0 or 1: reflect about the centre plane of axis i */
+    double generic[9];     /* generic 3x3 matrix G, row-major (identity if unused) */
+    double disp[3];        /* displacement d of the volume centre (input voxels) */
+    double crop[3];        /* crop shift k (input voxels) */
+} ctaug_affine_params;
+
+/* ------------------------------------------------------------------------ */
+/* Host-side helpers                                                         */
+/* ------------------------------------------------------------------------ */
+
+const char *ctaug_status_string(ctaug_status s);
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int ctaug_version(void);
+
+/* Transform composition (the paper composes rotation, scaling, shearing,
+ * reflection and a generic affine, and sets b = c + d - A c so that the
+ * volume centre c moves by d; the crop generalises c to separate input and
+ * output centres):
+ *     A = G Rz(rot_z) Ry(rot_y) Rx(rot_x) H diag(scale) F
+ *     c_in = (in_dim - 1)/2,  c_out = (out_dim - 1)/2
+ *     b = c_in + disp + crop - A c_out        (so A c_out + b = c_in + disp + crop)
+ * Rx(t) = [[1,0,0],[0,cos t,-sin t],[0,sin t,cos t]] and cyclically for y, z;
+ * F = diag(1 - 2*reflect).  Host only, synchronous.  Writes M = [A|b]
+ * row-major 3x4 in FP64 to M64 and/or FP32 (round to nearest) to M32 (either
+ * may be NULL).  Errors: EINVAL (null prm or both outputs NULL, non-finite
+ * value), ESHAPE (negative dimension). */
+ctaug_status ctaug_affine_matrix(const ctaug_affine_params *prm, const int64_t in_dim[3],
+                                 const int64_t out_dim[3], double M64[12], float M32[12]);
+
+/* ------------------------------------------------------------------------ */
+/* Forward warps                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Fused affine augmentation of one volume (Sec. "GPU-accelerated data
+ * augmentation": I_affine(x) = I_in(A x + b), trilinear image, nearest
+ * labels, then noise and window).  Per output voxel p with coordinate q:
+ *   image: if on any axis q_i is not strictly inside (-1, n_i) (or is NaN),
+ *          V = fill; otherwise V is the trilinear interpolation of the eight
+ *          voxels around floor(q), with `fill` substituted for every corner
+ *          outside the volume (constant border).  Then the photometric chain
+ *          of `photo` (NULL = identity, out = V).
+ *   labels: j_i = floorf(q_i + 0.5f) (FP32; ties round up); lbl_out(p) =
+ *          lbl_in(j) if j is inside the volume, else label_fill.
+ * img_in: device, F32 or I16, any dims.  lbl_in: device I8 with img_in's dims,
+ * or NULL.  M: host float[12].  img_out: device F32 (output dims).  lbl_out:
+ * device I8 with img_out's dims, required iff lbl_in is given.  img_out and
+ * lbl_out must not alias the inputs.
+ * Errors: EINVAL (null required pointer, non-finite M or fill, bad photo,
+ * reserved != 0, label_fill outside int8), EDTYPE, ESHAPE (dims mismatch,
+ * > 2^31-1 elements), EHIP. */
+ctaug_status ctaug_warp_affine(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
+                               const float M[12], float fill, int32_t label_fill,
+                               const ctaug_photo *photo, ctaug_vol *img_out,
+                               ctaug_vol *lbl_out, void *stream);
+
+/* As ctaug_warp_affine with a dense displacement field added to the affine
+ * coordinate: q_i = (A p + b)_i + u_i(p) (one FP32 addition).  disp: device
+ * float32 SoA [3][Xo][Yo][Zo] on the OUTPUT grid, in input-voxel units.
+ * Errors: as ctaug_warp_affine, plus EINVAL for a NULL disp. */
+ctaug_status ctaug_warp_displacement(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
+                                     const float M[12], const float *disp, float fill,
+                                     int32_t label_fill, const ctaug_photo *photo,
+                                     ctaug_vol *img_out, ctaug_vol *lbl_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Photometric transform and noise                                           */
+/* ------------------------------------------------------------------------ */
+
+/* In-place photometric chain (see ctaug_photo) on a F32 volume, voxel index v
+ * = linear index in the volume.  Bit-identical to the same chain fused into
+ * ctaug_warp_affine.  Errors: EINVAL, EDTYPE (not F32), ESHAPE, EHIP. */
+ctaug_status ctaug_photometric_noise(ctaug_vol *inout, const ctaug_photo *photo, void *stream);
+
+/* Noise generator (replaces the per-thread cuRAND generators of the paper's
+ * noise paragraph by a stateless counter-based generator).  For voxel index
+ * v, Philox4x32-10 (Salmon et al., SC'11) is evaluated at counter
+ * (lo32(v>>2), hi32(v>>2), volume_id, 0) with key (lo32(seed), hi32(seed)),
+ * giving words w0..w3.  Uniforms U(w) = ((w >> 9) + 0.5) * 2^-23.  Box-Muller
+ * on pair k = (v & 3) >> 1: r = sqrt(-2 ln U(w_2k)), theta = 2 pi U(w_2k+1);
+ * n(v) = r cos(theta) for even v, r sin(theta) for odd v.
+ * Writes, for v = v0 .. v0+n-1, gauss[v - v0] = n(v) (device float*, may be
+ * NULL) and, for the groups g = v0>>2 .. (v0+n-1)>>2, words[4*(g - (v0>>2)) + k]
+ * = w_k (device uint32*, may be NULL).  Errors: EINVAL (n < 0, overflow), EHIP. */
+ctaug_status ctaug_noise(uint64_t seed, uint32_t volume_id, uint64_t v0, int64_t n,
+                         float *gauss, uint32_t *words, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Adjoints (not in the paper)                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes needed by the backward calls for an output volume of
+ * out_dim (0 for an empty volume, or on bad dims). */
+size_t ctaug_warp_backward_workspace(const int64_t out_dim[3]);
+
+/* Adjoint of the affine warp's image path (photometrics excluded).  With
+ * weights w_c(p) of the in-volume corners c of the cell floor(q(p)):
+ *   grad_img[c] += sum_p w_c(p) grad_out(p)        (FP32 atomics; accumulates)
+ *   grad_M[i][j] = sum_p grad_out(p) dV/dq_i(p) [x,y,z,1]_j   (overwritten)
+ * dV/dq is the derivative of the interpolant on the cell floor(q) (fill
+ * corners included, i.e. the right derivative at integer q); samples outside
+ * (-1, n) contribute nothing.  img_in: device F32/I16; grad_out: device F32
+ * with the output dims; grad_img: device F32 with img_in's dims, or NULL;
+ * grad_M: device double[12], or NULL.  ws: device workspace of at least
+ * ctaug_warp_backward_workspace(out dims) bytes (required when grad_M is
+ * given).  grad_M is reduced deterministically in FP64.
+ * Errors: EINVAL, EDTYPE, ESHAPE, EWORKSPACE, EHIP. */
+ctaug_status ctaug_warp_affine_backward(const ctaug_vol *img_in, const float M[12], float fill,
+                                        const ctaug_vol *grad_out, ctaug_vol *grad_img,
+                                        double *grad_M, void *ws, size_t ws_bytes,
+                                        void *stream);
+
+/* Adjoint of ctaug_warp_displacement's image path: as above, plus
+ * grad_disp[i](p) = grad_out(p) dV/dq_i(p) (device float SoA [3][Xo][Yo][Zo],
+ * overwritten, or NULL). */
+ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in, const float M[12],
+                                              const float *disp, float fill,
+                                              const ctaug_vol *grad_out, ctaug_vol *grad_img,
+                                              double *grad_M, float *grad_disp, void *ws,
+                                              size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Cubic B-spline displacement (uniform cubic free-form deformation,         */
+/* Rueckert et al., IEEE TMI 1999; not in the paper)                         */
+/* ------------------------------------------------------------------------ */
+
+/* disp[i](p) = sum_{a,b,c=0..3} B_a(t_x) B_b(t_y) B_c(t_z) ctrl[i][ix+a][iy+b][iz+c]
+ * where, per axis k, h = (n_k - 1)/(G_k - 3), s = p_k / h, i = min(floor(s),
+ * G_k - 4), t = s - i (t = 0, i = 0 when n_k = 1), and B0 = (1-t)^3/6,
+ * B1 = (3t^3 - 6t^2 + 4)/6, B2 = (-3t^3 + 3t^2 + 3t + 1)/6, B3 = t^3/6: control
+ * j sits at output coordinate (j - 1) h.  ctrl: device float [3][Gx][Gy][Gz]
+ * with 4 <= G_k <= 64; disp: device float SoA [3][Xo][Yo][Zo].
+ * Errors: EINVAL, ESHAPE, EHIP. */
+ctaug_status ctaug_bspline_upsample(const float *ctrl, const int64_t G[3],
+                                    const int64_t out_dim[3], float *disp, void *stream);
+
+/* Workspace bytes for ctaug_bspline_upsample_adjoint. */
+size_t ctaug_bspline_adjoint_workspace(const int64_t out_dim[3], const int64_t G[3]);
+
+/* Adjoint: grad_ctrl = B^T grad_disp (device float [3][Gx][Gy][Gz], overwritten),
+ * reduced deterministically in FP64.  Errors: EINVAL, ESHAPE, EWORKSPACE, EHIP. */
+ctaug_status ctaug_bspline_upsample_adjoint(const float *grad_disp, const int64_t out_dim[3],
+                                            const int64_t G[3], float *grad_ctrl, void *ws,
+                                            size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched augmentation of volumes of uneven sizes (the paper augments a     */
+/* whole training batch through a job queue; here one launch covers it)      */
+/* ------------------------------------------------------------------------ */
+
+/* One job: exactly the arguments of ctaug_warp_affine.  lbl_in.data == NULL
+ * means no labels (then lbl_out is ignored); photo.flags bit 31 set means
+ * "no photometrics". */
+typedef struct {
+    ctaug_vol img_in, lbl_in, img_out, lbl_out;
+    float M[12];
+    float fill;
+    int32_t label_fill;
+    ctaug_photo photo;
+} ctaug_job;
+
+#define CTAUG_PHOTO_NONE 0x80000000u
+
+/* Launch shape: output tile (voxels along x, y, z; z a multiple of 4), and
+ * the number of resident workgroups per CU for the persistent launch
+ * (0 = one workgroup per tile, non-persistent). */
+typedef struct {
+    int32_t tile[3];
+    int32_t wg_per_cu;
+} ctaug_tuning;
+
+typedef struct ctaug_batch_plan ctaug_batch_plan;
+
+/* Create a plan for n_jobs jobs whose shapes are those of jobs[] (host
+ * array).  Allocates the device job table and pinned staging (freed by
+ * ctaug_batch_plan_destroy).  tune == NULL picks the default launch shape.
+ * Errors: EINVAL, EDTYPE, ESHAPE, EHIP. */
+ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n_jobs,
+                                     const ctaug_tuning *tune, ctaug_batch_plan **plan);
+
+/* Replace the jobs' contents (pointers, matrices, photometrics).  Every job
+ * must keep the output dims it had at plan creation.  Waits (host side) for
+ * the previous launch's table upload to finish before overwriting staging. */
+ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jobs);
+
+/* Enqueue: upload the job table (async copy from pinned staging) and run one
+ * persistent launch that warps every job.  Results equal ctaug_warp_affine
+ * on each job, bit for bit. */
+ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *plan, void *stream);
+
+/* Capture ctaug_batch_plan_launch on `stream` into a HIP graph owned by the
+ * plan (replacing any earlier one); ctaug_batch_plan_replay then launches it.
+ * The graph reads the staging buffer at replay time, so updates between
+ * replays need no re-capture. */
+ctaug_status ctaug_batch_plan_capture(ctaug_batch_plan *plan, void *stream);
+ctaug_status ctaug_batch_plan_replay(ctaug_batch_plan *plan, void *stream);
+
+/* Time each candidate launch shape on the plan's current jobs (HIP events,
+ * `reps` launches each, after one warm-up) and keep the fastest in the plan.
+ * The jobs' outputs are overwritten (with identical results).  Synchronises
+ * `stream`.  best (host, may be NULL) receives the choice; times_ms (host
+ * float[n_cand], may be NULL) the mean time per launch of each candidate. */
+ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *plan, const ctaug_tuning *cand,
+                                       int32_t n_cand, int32_t reps, void *stream,
+                                       ctaug_tuning *best, float *times_ms);
+
+ctaug_status ctaug_batch_plan_get_tuning(const ctaug_batch_plan *plan, ctaug_tuning *out);
+ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTAUG_H */

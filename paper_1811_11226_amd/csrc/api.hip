@@ -1,0 +1,784 @@
+// api.hip -- the C ABI declared in include/ctaug.h: argument validation, job
+// descriptor construction, launch configuration and the batch plan
+// (device job table + pinned staging + HIP graph + autotuner).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ctaug.h"
+#include "device_common.h"
+#include "launch.h"
+
+using namespace ctaug;
+
+namespace {
+
+constexpr int64_t kMaxElems = 2147483647LL;   // int32 linear indices in the kernels
+constexpr Tiling kDefaultTiling = {2, 3, 5};   // 4 x 8 x 32 output voxels per workgroup
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+ctaug_status hip_status(hipError_t e) { return e == hipSuccess ? CTAUG_OK : CTAUG_EHIP; }
+
+int64_t nelem(const int64_t d[3]) { return d[0] * d[1] * d[2]; }
+
+bool dims_valid(const int64_t d[3])
+{
+    if (d[0] < 0 || d[1] < 0 || d[2] < 0)
+        return false;
+    if (d[0] == 0 || d[1] == 0 || d[2] == 0)
+        return true;
+    if (d[0] > kMaxElems || d[1] > kMaxElems || d[2] > kMaxElems)
+        return false;
+    return d[0] * d[1] <= kMaxElems && d[0] * d[1] * d[2] <= kMaxElems;
+}
+
+// Validate a volume argument; `allowed` is a bit set of dtypes.
+ctaug_status check_vol(const ctaug_vol *v, unsigned allowed)
+{
+    if (!v || v->reserved != 0)
+        return CTAUG_EINVAL;
+    if (v->dtype < 0 || v->dtype > 2 || !(allowed & (1u << v->dtype)))
+        return CTAUG_EDTYPE;
+    if (!dims_valid(v->dim))
+        return CTAUG_ESHAPE;
+    if (!v->data && nelem(v->dim) > 0)
+        return CTAUG_EINVAL;
+    return CTAUG_OK;
+}
+
+bool same_dims(const ctaug_vol *a, const ctaug_vol *b)
+{
+    return a->dim[0] == b->dim[0] && a->dim[1] == b->dim[1] && a->dim[2] == b->dim[2];
+}
+
+bool finite_all(const float *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i]))
+            return false;
+    return true;
+}
+
+ctaug_status check_photo(const ctaug_photo *p)
+{
+    if (!p)
+        return CTAUG_OK;
+    const float vals[6] = {p->gain, p->offset, p->sigma, p->win_lo, p->win_hi, p->gamma};
+    if (!finite_all(vals, 6) || p->sigma < 0.0f || !(p->gamma > 0.0f))
+        return CTAUG_EINVAL;
+    if (p->flags & ~(uint32_t)CTAUG_PHOTO_WINDOW)
+        return CTAUG_EINVAL;
+    if ((p->flags & CTAUG_PHOTO_WINDOW) && !(p->win_hi > p->win_lo))
+        return CTAUG_EINVAL;
+    return CTAUG_OK;
+}
+
+void set_photo(FwdJob &J, const ctaug_photo *p)
+{
+    J.gain = 1.0f;
+    J.offset = 0.0f;
+    J.sigma = 0.0f;
+    J.win_lo = 0.0f;
+    J.inv_range = 1.0f;
+    J.gamma = 1.0f;
+    J.vol_id = J.key0 = J.key1 = 0;
+    if (!p)
+        return;
+    J.flags |= kFlagPhoto;
+    J.gain = p->gain;
+    J.offset = p->offset;
+    J.sigma = p->sigma;
+    J.win_lo = p->win_lo;
+    J.inv_range = (float)(1.0 / ((double)p->win_hi - (double)p->win_lo));
+    J.gamma = p->gamma;
+    J.vol_id = p->volume_id;
+    J.key0 = (uint32_t)p->seed;
+    J.key1 = (uint32_t)(p->seed >> 32);
+    if (p->sigma > 0.0f)
+        J.flags |= kFlagNoise;
+    if (p->flags & CTAUG_PHOTO_WINDOW) {
+        J.flags |= kFlagWindow;
+        if (p->gamma != 1.0f)
+            J.flags |= kFlagGamma;
+    }
+}
+
+Photo photo_from_job(const FwdJob &J)
+{
+    Photo P;
+    P.flags = J.flags;
+    P.gain = J.gain;
+    P.offset = J.offset;
+    P.sigma = J.sigma;
+    P.win_lo = J.win_lo;
+    P.inv_range = J.inv_range;
+    P.gamma = J.gamma;
+    return P;
+}
+
+void set_tiles(FwdJob &J, const Tiling &TL)
+{
+    J.tiles_x = (J.ox + (1 << TL.lx) - 1) >> TL.lx;
+    J.tiles_y = (J.oy + (1 << TL.ly) - 1) >> TL.ly;
+    J.tiles_z = (J.oz + (1 << TL.lz) - 1) >> TL.lz;
+}
+
+// Validate the arguments of one forward warp and build its descriptor.
+ctaug_status make_job(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const float *M,
+                      const float *disp, bool need_disp, float fill, int32_t label_fill,
+                      const ctaug_photo *photo, const ctaug_vol *img_out,
+                      const ctaug_vol *lbl_out, const Tiling &TL, FwdJob &J)
+{
+    ctaug_status st;
+    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+        return st;
+    if ((st = check_vol(img_out, 1u << CTAUG_F32)) != CTAUG_OK)
+        return st;
+    if (lbl_in) {
+        if ((st = check_vol(lbl_in, 1u << CTAUG_I8)) != CTAUG_OK)
+            return st;
+        if (!same_dims(lbl_in, img_in))
+            return CTAUG_ESHAPE;
+        if (!lbl_out)
+            return CTAUG_EINVAL;
+        if ((st = check_vol(lbl_out, 1u << CTAUG_I8)) != CTAUG_OK)
+            return st;
+        if (!same_dims(lbl_out, img_out))
+            return CTAUG_ESHAPE;
+    }
+    if (!M || !finite_all(M, 12) || !std::isfinite(fill))
+        return CTAUG_EINVAL;
+    if (label_fill < -128 || label_fill > 127)
+        return CTAUG_EINVAL;
+    if ((st = check_photo(photo)) != CTAUG_OK)
+        return st;
+    const int64_t nout = nelem(img_out->dim);
+    if (need_disp) {
+        if (!disp && nout > 0)
+            return CTAUG_EINVAL;
+        if (3 * nout > kMaxElems)
+            return CTAUG_ESHAPE;
+    }
+    std::memset(&J, 0, sizeof J);
+    J.img = img_in->data;
+    J.lbl = lbl_in ? static_cast<const int8_t *>(lbl_in->data) : nullptr;
+    J.out = static_cast<float *>(img_out->data);
+    J.lout = lbl_in ? static_cast<int8_t *>(lbl_out->data) : nullptr;
+    J.disp = need_disp ? disp : nullptr;
+    J.dtype = img_in->dtype;
+    J.nx = (int32_t)img_in->dim[0];
+    J.ny = (int32_t)img_in->dim[1];
+    J.nz = (int32_t)img_in->dim[2];
+    J.ox = (int32_t)img_out->dim[0];
+    J.oy = (int32_t)img_out->dim[1];
+    J.oz = (int32_t)img_out->dim[2];
+    std::memcpy(J.M, M, sizeof J.M);
+    // Bound on the FP32 rounding of q over the output box: three fmaf roundings
+    // of partial sums bounded by S_i = sum_j |A_ij| (n_j - 1) + |b_i|.
+    const int64_t last[3] = {std::max<int64_t>(J.ox - 1, 0), std::max<int64_t>(J.oy - 1, 0),
+                             std::max<int64_t>(J.oz - 1, 0)};
+    for (int i = 0; i < 3; ++i) {
+        double S = std::fabs((double)M[4 * i + 3]);
+        for (int j = 0; j < 3; ++j)
+            S += std::fabs((double)M[4 * i + j]) * (double)last[j];
+        J.delta[i] = (float)((S + 1.0) * std::ldexp(1.0, -20));
+    }
+    J.fill = fill;
+    J.label_fill = label_fill;
+    if (J.lbl)
+        J.flags |= kFlagLabels;
+    set_photo(J, photo);
+    const bool out_aligned = (reinterpret_cast<uintptr_t>(J.out) & 15u) == 0;
+    const bool lbl_aligned = !J.lout || (reinterpret_cast<uintptr_t>(J.lout) & 3u) == 0;
+    if (J.oz % 4 == 0 && out_aligned && lbl_aligned)
+        J.flags |= kFlagVec;
+    set_tiles(J, TL);
+    return CTAUG_OK;
+}
+
+bool empty(const FwdJob &J) { return J.ox == 0 || J.oy == 0 || J.oz == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" const char *ctaug_status_string(ctaug_status s)
+{
+    switch (s) {
+    case CTAUG_OK: return "ok";
+    case CTAUG_EINVAL: return "invalid argument";
+    case CTAUG_EDTYPE: return "unsupported dtype";
+    case CTAUG_ESHAPE: return "invalid or inconsistent shape";
+    case CTAUG_EWORKSPACE: return "workspace missing or too small";
+    case CTAUG_EHIP: return "HIP runtime error";
+    case CTAUG_ENODEV: return "no usable gfx950 device";
+    }
+    return "unknown status";
+}
+
+extern "C" int ctaug_version(void) { return 10000; }
+
+extern "C" ctaug_status ctaug_affine_matrix(const ctaug_affine_params *p, const int64_t in_dim[3],
+                                            const int64_t out_dim[3], double M64[12],
+                                            float M32[12])
+{
+    if (!p || !in_dim || !out_dim || (!M64 && !M32))
+        return CTAUG_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (in_dim[i] < 0 || out_dim[i] < 0)
+            return CTAUG_ESHAPE;
+    const double *all = reinterpret_cast<const double *>(p);
+    for (size_t i = 0; i < sizeof(ctaug_affine_params) / sizeof(double); ++i)
+        if (!std::isfinite(all[i]))
+            return CTAUG_EINVAL;
+    // factors, each a 3x3 row-major matrix
+    double f[7][9];
+    std::memcpy(f[0], p->generic, sizeof f[0]);
+    const double cz = std::cos(p->rot[2]), sz = std::sin(p->rot[2]);
+    const double cy = std::cos(p->rot[1]), sy = std::sin(p->rot[1]);
+    const double cx = std::cos(p->rot[0]), sx = std::sin(p->rot[0]);
+    const double Rz[9] = {cz, -sz, 0, sz, cz, 0, 0, 0, 1};
+    const double Ry[9] = {cy, 0, sy, 0, 1, 0, -sy, 0, cy};
+    const double Rx[9] = {1, 0, 0, 0, cx, -sx, 0, sx, cx};
+    const double H[9] = {1, p->shear[0], p->shear[1], 0, 1, p->shear[2], 0, 0, 1};
+    const double S[9] = {p->scale[0], 0, 0, 0, p->scale[1], 0, 0, 0, p->scale[2]};
+    double F[9] = {0};
+    for (int i = 0; i < 3; ++i)
+        F[4 * i] = p->reflect[i] != 0.0 ? -1.0 : 1.0;
+    std::memcpy(f[1], Rz, sizeof Rz);
+    std::memcpy(f[2], Ry, sizeof Ry);
+    std::memcpy(f[3], Rx, sizeof Rx);
+    std::memcpy(f[4], H, sizeof H);
+    std::memcpy(f[5], S, sizeof S);
+    std::memcpy(f[6], F, sizeof F);
+    double A[9];
+    std::memcpy(A, f[0], sizeof A);
+    for (int k = 1; k < 7; ++k) {
+        double R[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                R[3 * i + j] = A[3 * i] * f[k][j] + A[3 * i + 1] * f[k][3 + j] +
+                               A[3 * i + 2] * f[k][6 + j];
+        std::memcpy(A, R, sizeof A);
+    }
+    double out[12];
+    for (int i = 0; i < 3; ++i) {
+        double Ac = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            out[4 * i + j] = A[3 * i + j];
+            Ac += A[3 * i + j] * (0.5 * (double)(out_dim[j] - 1));
+        }
+        out[4 * i + 3] = 0.5 * (double)(in_dim[i] - 1) + p->disp[i] + p->crop[i] - Ac;
+    }
+    for (int k = 0; k < 12; ++k) {
+        if (M64)
+            M64[k] = out[k];
+        if (M32)
+            M32[k] = (float)out[k];
+    }
+    return CTAUG_OK;
+}
+
+static ctaug_status warp_impl(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const float M[12],
+                              const float *disp, bool need_disp, float fill, int32_t label_fill,
+                              const ctaug_photo *photo, ctaug_vol *img_out, ctaug_vol *lbl_out,
+                              void *stream)
+{
+    FwdJob J;
+    ctaug_status st = make_job(img_in, lbl_in, M, disp, need_disp, fill, label_fill, photo,
+                               img_out, lbl_out, kDefaultTiling, J);
+    if (st != CTAUG_OK)
+        return st;
+    if (empty(J))
+        return CTAUG_OK;
+    return hip_status(launch_warp_single(J, kDefaultTiling, as_stream(stream)));
+}
+
+extern "C" ctaug_status ctaug_warp_affine(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
+                                          const float M[12], float fill, int32_t label_fill,
+                                          const ctaug_photo *photo, ctaug_vol *img_out,
+                                          ctaug_vol *lbl_out, void *stream)
+{
+    return warp_impl(img_in, lbl_in, M, nullptr, false, fill, label_fill, photo, img_out, lbl_out,
+                     stream);
+}
+
+extern "C" ctaug_status ctaug_warp_displacement(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
+                                                const float M[12], const float *disp, float fill,
+                                                int32_t label_fill, const ctaug_photo *photo,
+                                                ctaug_vol *img_out, ctaug_vol *lbl_out,
+                                                void *stream)
+{
+    return warp_impl(img_in, lbl_in, M, disp, true, fill, label_fill, photo, img_out, lbl_out,
+                     stream);
+}
+
+extern "C" ctaug_status ctaug_photometric_noise(ctaug_vol *inout, const ctaug_photo *photo,
+                                                void *stream)
+{
+    ctaug_status st;
+    if ((st = check_vol(inout, 1u << CTAUG_F32)) != CTAUG_OK)
+        return st;
+    if (!photo)
+        return CTAUG_EINVAL;
+    if ((st = check_photo(photo)) != CTAUG_OK)
+        return st;
+    FwdJob J;
+    std::memset(&J, 0, sizeof J);
+    set_photo(J, photo);
+    const int64_t n = nelem(inout->dim);
+    if (n == 0)
+        return CTAUG_OK;
+    const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(inout->data) & 15u) == 0;
+    return hip_status(launch_photometric(static_cast<float *>(inout->data), n, photo_from_job(J),
+                                         J.vol_id, J.key0, J.key1, vec, as_stream(stream)));
+}
+
+extern "C" ctaug_status ctaug_noise(uint64_t seed, uint32_t volume_id, uint64_t v0, int64_t n,
+                                    float *gauss, uint32_t *words, void *stream)
+{
+    if (n < 0 || (uint64_t)n > ~(uint64_t)0 - v0)
+        return CTAUG_EINVAL;
+    if (n == 0 || (!gauss && !words))
+        return CTAUG_OK;
+    return hip_status(launch_noise(v0, n, volume_id, (uint32_t)seed, (uint32_t)(seed >> 32), gauss,
+                                   words, as_stream(stream)));
+}
+
+extern "C" size_t ctaug_warp_backward_workspace(const int64_t out_dim[3])
+{
+    if (!out_dim || !dims_valid(out_dim))
+        return 0;
+    return (size_t)bwd_num_tiles(out_dim[0], out_dim[1], out_dim[2]) * 12 * sizeof(double);
+}
+
+static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], const float *disp,
+                                  bool need_disp, float fill, const ctaug_vol *grad_out,
+                                  ctaug_vol *grad_img, double *grad_M, float *grad_disp, void *ws,
+                                  size_t ws_bytes, void *stream)
+{
+    ctaug_status st;
+    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+        return st;
+    if ((st = check_vol(grad_out, 1u << CTAUG_F32)) != CTAUG_OK)
+        return st;
+    if (grad_img) {
+        if ((st = check_vol(grad_img, 1u << CTAUG_F32)) != CTAUG_OK)
+            return st;
+        if (!same_dims(grad_img, img_in))
+            return CTAUG_ESHAPE;
+    }
+    if (need_disp && grad_disp && 3 * nelem(grad_out->dim) > kMaxElems)
+        return CTAUG_ESHAPE;
+    if (grad_M) {
+        const size_t need = ctaug_warp_backward_workspace(grad_out->dim);
+        if (need > 0 && (!ws || ws_bytes < need))
+            return CTAUG_EWORKSPACE;
+    }
+    FwdJob J;
+    // the gradient volume plays the part of the forward output (dims only)
+    ctaug_vol out_like = *grad_out;
+    st = make_job(img_in, nullptr, M, disp, need_disp, fill, 0, nullptr, &out_like, nullptr,
+                  kDefaultTiling, J);
+    if (st != CTAUG_OK)
+        return st;
+    J.out = nullptr;
+    if (empty(J) && !grad_M)
+        return CTAUG_OK;
+    return hip_status(launch_warp_bwd(J, static_cast<const float *>(grad_out->data),
+                                      grad_img ? static_cast<float *>(grad_img->data) : nullptr,
+                                      need_disp ? grad_disp : nullptr, grad_M,
+                                      static_cast<double *>(ws), as_stream(stream)));
+}
+
+extern "C" ctaug_status ctaug_warp_affine_backward(const ctaug_vol *img_in, const float M[12],
+                                                   float fill, const ctaug_vol *grad_out,
+                                                   ctaug_vol *grad_img, double *grad_M, void *ws,
+                                                   size_t ws_bytes, void *stream)
+{
+    return backward_impl(img_in, M, nullptr, false, fill, grad_out, grad_img, grad_M, nullptr, ws,
+                         ws_bytes, stream);
+}
+
+extern "C" ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in,
+                                                         const float M[12], const float *disp,
+                                                         float fill, const ctaug_vol *grad_out,
+                                                         ctaug_vol *grad_img, double *grad_M,
+                                                         float *grad_disp, void *ws,
+                                                         size_t ws_bytes, void *stream)
+{
+    return backward_impl(img_in, M, disp, true, fill, grad_out, grad_img, grad_M, grad_disp, ws,
+                         ws_bytes, stream);
+}
+
+static ctaug_status check_grid(const int64_t G[3], const int64_t od[3])
+{
+    if (!G || !od)
+        return CTAUG_EINVAL;
+    if (!dims_valid(od) || 3 * nelem(od) > kMaxElems)
+        return CTAUG_ESHAPE;
+    for (int i = 0; i < 3; ++i)
+        if (G[i] < 4 || G[i] > bspline_max_grid())
+            return CTAUG_ESHAPE;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_bspline_upsample(const float *ctrl, const int64_t G[3],
+                                               const int64_t out_dim[3], float *disp, void *stream)
+{
+    ctaug_status st = check_grid(G, out_dim);
+    if (st != CTAUG_OK)
+        return st;
+    if (nelem(out_dim) == 0)
+        return CTAUG_OK;
+    if (!ctrl || !disp)
+        return CTAUG_EINVAL;
+    const bool vec = out_dim[2] % 4 == 0 && (reinterpret_cast<uintptr_t>(disp) & 15u) == 0;
+    return hip_status(launch_bspline_up(ctrl, G, out_dim, disp, vec, as_stream(stream)));
+}
+
+extern "C" size_t ctaug_bspline_adjoint_workspace(const int64_t out_dim[3], const int64_t G[3])
+{
+    if (check_grid(G, out_dim) != CTAUG_OK)
+        return 0;
+    return (size_t)bspline_adj_ws_bytes(out_dim, G);
+}
+
+extern "C" ctaug_status ctaug_bspline_upsample_adjoint(const float *grad_disp,
+                                                       const int64_t out_dim[3],
+                                                       const int64_t G[3], float *grad_ctrl,
+                                                       void *ws, size_t ws_bytes, void *stream)
+{
+    ctaug_status st = check_grid(G, out_dim);
+    if (st != CTAUG_OK)
+        return st;
+    if (!grad_ctrl || (nelem(out_dim) > 0 && !grad_disp))
+        return CTAUG_EINVAL;
+    const size_t need = ctaug_bspline_adjoint_workspace(out_dim, G);
+    if (need > 0 && (!ws || ws_bytes < need))
+        return CTAUG_EWORKSPACE;
+    return hip_status(launch_bspline_adj(grad_disp, out_dim, G, grad_ctrl,
+                                         static_cast<double *>(ws), as_stream(stream)));
+}
+
+// ---------------------------------------------------------------------------
+// Batch plan
+// ---------------------------------------------------------------------------
+
+struct ctaug_batch_plan {
+    int32_t n = 0;
+    std::vector<int32_t> out_dims;      // 3 per job, fixed at creation
+    std::vector<FwdJob> jobs;           // current descriptors (host copy)
+    FwdJob *staging = nullptr;          // pinned host
+    FwdJob *table = nullptr;            // device
+    int32_t *prefix_dev = nullptr;      // device, n + 1
+    int32_t total = 0;
+    ctaug_tuning tune{};
+    Tiling TL = kDefaultTiling;
+    int32_t grid = 0;
+    int num_cu = 256;
+    hipEvent_t upload_done = nullptr;
+    bool upload_recorded = false;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v)
+        ++l;
+    return (1 << l) == v ? l : -1;
+}
+
+ctaug_status tiling_of(const ctaug_tuning *t, Tiling &TL)
+{
+    if (!t) {
+        TL = kDefaultTiling;
+        return CTAUG_OK;
+    }
+    const int lx = ilog2(t->tile[0]), ly = ilog2(t->tile[1]), lz = ilog2(t->tile[2]);
+    if (lx < 0 || ly < 0 || lz < 2 || lx + ly + lz > 14 || t->wg_per_cu < 0 || t->wg_per_cu > 32)
+        return CTAUG_EINVAL;
+    TL = {lx, ly, lz};
+    return CTAUG_OK;
+}
+
+ctaug_status job_from_public(const ctaug_job &j, const Tiling &TL, FwdJob &J)
+{
+    const bool has_lbl = j.lbl_in.data != nullptr;
+    const bool has_photo = !(j.photo.flags & CTAUG_PHOTO_NONE);
+    return make_job(&j.img_in, has_lbl ? &j.lbl_in : nullptr, j.M, nullptr, false, j.fill,
+                    j.label_fill, has_photo ? &j.photo : nullptr, &j.img_out,
+                    has_lbl ? &j.lbl_out : nullptr, TL, J);
+}
+
+void destroy_graph(ctaug_batch_plan *p)
+{
+    if (p->exec) {
+        (void)hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+}
+
+// Recompute tile counts / prefix sums / grid for the plan's tiling and upload
+// the prefix table (synchronous: only at creation and retuning).
+ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
+{
+    Tiling TL;
+    ctaug_status st = tiling_of(&t, TL);
+    if (st != CTAUG_OK)
+        return st;
+    std::vector<int32_t> prefix(p->n + 1, 0);
+    int64_t total = 0;
+    for (int i = 0; i < p->n; ++i) {
+        set_tiles(p->jobs[i], TL);
+        prefix[i] = (int32_t)total;
+        total += (int64_t)p->jobs[i].tiles_x * p->jobs[i].tiles_y * p->jobs[i].tiles_z;
+    }
+    if (total > (int64_t)kMaxElems)
+        return CTAUG_ESHAPE;
+    prefix[p->n] = (int32_t)total;
+    if (hipMemcpy(p->prefix_dev, prefix.data(), sizeof(int32_t) * (p->n + 1),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return CTAUG_EHIP;
+    if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
+        return CTAUG_EHIP;
+    std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
+    p->TL = TL;
+    p->tune = t;
+    p->total = (int32_t)total;
+    const int64_t tiles8 = ((total + 7) / 8) * 8;
+    int64_t grid = t.wg_per_cu > 0 ? (int64_t)p->num_cu * t.wg_per_cu : tiles8;
+    grid = std::max<int64_t>(8, (grid / 8) * 8);
+    p->grid = (int32_t)std::min<int64_t>(grid, std::max<int64_t>(tiles8, 8));
+    destroy_graph(p);
+    return CTAUG_OK;
+}
+
+ctaug_status enqueue(ctaug_batch_plan *p, hipStream_t s)
+{
+    if (hipMemcpyAsync(p->table, p->staging, sizeof(FwdJob) * p->n, hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return CTAUG_EHIP;
+    return hip_status(launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL, s));
+}
+
+}  // namespace
+
+extern "C" ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *p)
+{
+    if (!p)
+        return CTAUG_EINVAL;
+    destroy_graph(p);
+    if (p->upload_done)
+        (void)hipEventDestroy(p->upload_done);
+    if (p->staging)
+        (void)hipHostFree(p->staging);
+    if (p->table)
+        (void)hipFree(p->table);
+    if (p->prefix_dev)
+        (void)hipFree(p->prefix_dev);
+    delete p;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n_jobs,
+                                                const ctaug_tuning *tune, ctaug_batch_plan **out)
+{
+    if (!jobs || !out || n_jobs <= 0 || n_jobs > (1 << 20))
+        return CTAUG_EINVAL;
+    Tiling TL;
+    ctaug_status st = tiling_of(tune, TL);
+    if (st != CTAUG_OK)
+        return st;
+    ctaug_batch_plan *p = new (std::nothrow) ctaug_batch_plan();
+    if (!p)
+        return CTAUG_EINVAL;
+    p->n = n_jobs;
+    p->jobs.resize(n_jobs);
+    p->out_dims.resize(3 * (size_t)n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        st = job_from_public(jobs[i], TL, p->jobs[i]);
+        if (st != CTAUG_OK) {
+            delete p;
+            return st;
+        }
+        p->out_dims[3 * i + 0] = p->jobs[i].ox;
+        p->out_dims[3 * i + 1] = p->jobs[i].oy;
+        p->out_dims[3 * i + 2] = p->jobs[i].oz;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete p;
+        return CTAUG_ENODEV;
+    }
+    p->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (hipHostMalloc(reinterpret_cast<void **>(&p->staging), sizeof(FwdJob) * n_jobs,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&p->table), sizeof(FwdJob) * n_jobs) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&p->prefix_dev), sizeof(int32_t) * (n_jobs + 1)) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming) != hipSuccess) {
+        ctaug_batch_plan_destroy(p);
+        return CTAUG_EHIP;
+    }
+    ctaug_tuning t = tune ? *tune : ctaug_tuning{{4, 8, 32}, 0};
+    st = apply_tiling(p, t);
+    if (st != CTAUG_OK) {
+        ctaug_batch_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug_job *jobs)
+{
+    if (!p || !jobs)
+        return CTAUG_EINVAL;
+    std::vector<FwdJob> next(p->n);
+    for (int i = 0; i < p->n; ++i) {
+        ctaug_status st = job_from_public(jobs[i], p->TL, next[i]);
+        if (st != CTAUG_OK)
+            return st;
+        if (next[i].ox != p->out_dims[3 * i] || next[i].oy != p->out_dims[3 * i + 1] ||
+            next[i].oz != p->out_dims[3 * i + 2])
+            return CTAUG_ESHAPE;
+    }
+    if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
+        return CTAUG_EHIP;
+    p->jobs = next;
+    std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *p, void *stream)
+{
+    if (!p)
+        return CTAUG_EINVAL;
+    hipStream_t s = as_stream(stream);
+    ctaug_status st = enqueue(p, s);
+    if (st != CTAUG_OK)
+        return st;
+    if (hipEventRecord(p->upload_done, s) != hipSuccess)
+        return CTAUG_EHIP;
+    p->upload_recorded = true;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_capture(ctaug_batch_plan *p, void *stream)
+{
+    if (!p)
+        return CTAUG_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (!s)
+        return CTAUG_EINVAL;             // the null stream cannot be captured
+    destroy_graph(p);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return CTAUG_EHIP;
+    ctaug_status st = enqueue(p, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != CTAUG_OK || e != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return st != CTAUG_OK ? st : CTAUG_EHIP;
+    }
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        p->exec = nullptr;
+        return CTAUG_EHIP;
+    }
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_replay(ctaug_batch_plan *p, void *stream)
+{
+    if (!p || !p->exec)
+        return CTAUG_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (hipGraphLaunch(p->exec, s) != hipSuccess)
+        return CTAUG_EHIP;
+    if (hipEventRecord(p->upload_done, s) != hipSuccess)
+        return CTAUG_EHIP;
+    p->upload_recorded = true;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_get_tuning(const ctaug_batch_plan *p, ctaug_tuning *out)
+{
+    if (!p || !out)
+        return CTAUG_EINVAL;
+    *out = p->tune;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *p, const ctaug_tuning *cand,
+                                                  int32_t n_cand, int32_t reps, void *stream,
+                                                  ctaug_tuning *best, float *times_ms)
+{
+    if (!p || !cand || n_cand <= 0 || reps <= 0)
+        return CTAUG_EINVAL;
+    for (int i = 0; i < n_cand; ++i) {
+        Tiling TL;
+        if (tiling_of(&cand[i], TL) != CTAUG_OK)
+            return CTAUG_EINVAL;
+    }
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return CTAUG_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CTAUG_EHIP;
+    }
+    const ctaug_tuning original = p->tune;
+    int best_i = -1;
+    float best_ms = 0.0f;
+    ctaug_status st = CTAUG_OK;
+    for (int i = 0; i < n_cand && st == CTAUG_OK; ++i) {
+        st = apply_tiling(p, cand[i]);
+        if (st != CTAUG_OK)
+            break;
+        st = ctaug_batch_plan_launch(p, stream);           // warm-up
+        if (st != CTAUG_OK)
+            break;
+        if (hipEventRecord(e0, s) != hipSuccess) {
+            st = CTAUG_EHIP;
+            break;
+        }
+        for (int r = 0; r < reps && st == CTAUG_OK; ++r)
+            st = ctaug_batch_plan_launch(p, stream);
+        if (st != CTAUG_OK)
+            break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = CTAUG_EHIP;
+            break;
+        }
+        ms /= (float)reps;
+        if (times_ms)
+            times_ms[i] = ms;
+        if (best_i < 0 || ms < best_ms) {
+            best_i = i;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != CTAUG_OK) {
+        (void)apply_tiling(p, original);
+        return st;
+    }
+    st = apply_tiling(p, cand[best_i]);
+    if (st == CTAUG_OK && best)
+        *best = cand[best_i];
+    return st;
+}

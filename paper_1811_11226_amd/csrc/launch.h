@@ -1,0 +1,30 @@
+// launch.h -- host-side launchers of the gfx950 kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace ctaug {
+
+hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s);
+hipError_t launch_warp_batch(const FwdJob *jobs_dev, const int32_t *prefix_dev, int32_t njobs,
+                             int32_t total_tiles, int32_t grid, const Tiling &TL, hipStream_t s);
+hipError_t launch_photometric(float *data, int64_t n, const Photo &P, uint32_t vol, uint32_t k0,
+                              uint32_t k1, bool vec, hipStream_t s);
+hipError_t launch_noise(uint64_t v0, int64_t n, uint32_t vol, uint32_t k0, uint32_t k1,
+                        float *gauss, uint32_t *words, hipStream_t s);
+
+int64_t bwd_num_tiles(int64_t ox, int64_t oy, int64_t oz);
+hipError_t launch_warp_bwd(const FwdJob &J, const float *g, float *g_img, float *g_disp,
+                           double *g_M, double *partials, hipStream_t s);
+
+int bspline_max_grid();
+int64_t bspline_adj_ws_bytes(const int64_t od[3], const int64_t G[3]);
+hipError_t launch_bspline_up(const float *ctrl, const int64_t G[3], const int64_t od[3],
+                             float *disp, bool vec, hipStream_t s);
+hipError_t launch_bspline_adj(const float *grad_disp, const int64_t od[3], const int64_t G[3],
+                              float *grad_ctrl, double *ws, hipStream_t s);
+
+}  // namespace ctaug

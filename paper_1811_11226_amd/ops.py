@@ -1,0 +1,310 @@
+"""Python entry points with the names of the C ABI (include/ctaug.h).
+
+Only argument marshalling happens here: torch CUDA tensors provide device
+memory and the current HIP stream, and every step runs in the library's
+kernels.  Volumes are contiguous [X][Y][Z] tensors (z fastest).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CTAUG_F32, CTAUG_I16, CTAUG_I8, CTAUG_PHOTO_NONE, CTAUG_PHOTO_WINDOW
+
+_DTYPES = {torch.float32: CTAUG_F32, torch.int16: CTAUG_I16, torch.int8: CTAUG_I8}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require(t, name, dtypes, ndim=3):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def vol(t):
+    v = _lib.Vol()
+    v.data = t.data_ptr() if t.numel() > 0 else None
+    v.dtype = _DTYPES[t.dtype]
+    v.reserved = 0
+    for i in range(3):
+        v.dim[i] = t.shape[i]
+    return v
+
+
+def _M32(M):
+    a = np.ascontiguousarray(np.asarray(M, dtype=np.float32).reshape(12))
+    return (ctypes.c_float * 12)(*a.tolist())
+
+
+def make_photo(photo):
+    """ctypes Photo from any object with gain, offset, sigma, win_lo, win_hi,
+    gamma, window, seed and volume_id attributes (None -> None)."""
+    if photo is None:
+        return None
+    p = _lib.Photo()
+    p.gain, p.offset, p.sigma = photo.gain, photo.offset, photo.sigma
+    p.win_lo, p.win_hi, p.gamma = photo.win_lo, photo.win_hi, photo.gamma
+    p.flags = CTAUG_PHOTO_WINDOW if photo.window else 0
+    p.volume_id = int(photo.volume_id)
+    p.seed = int(photo.seed)
+    return p
+
+
+def _ref(x):
+    return None if x is None else ctypes.byref(x)
+
+
+def affine_matrix(prm, in_dim, out_dim):
+    """[A|b] from the 27 raw transform draws (FP64 and FP32 copies)."""
+    prm = np.asarray(prm, dtype=np.float64).reshape(27)
+    p = _lib.AffineParams()
+    fields = [("rot", 0, 3), ("scale", 3, 3), ("shear", 6, 3), ("reflect", 9, 3),
+              ("generic", 12, 9), ("disp", 21, 3), ("crop", 24, 3)]
+    for name, off, n in fields:
+        arr = getattr(p, name)
+        for i in range(n):
+            arr[i] = float(prm[off + i])
+    idim = (ctypes.c_int64 * 3)(*[int(v) for v in in_dim])
+    odim = (ctypes.c_int64 * 3)(*[int(v) for v in out_dim])
+    M64 = (ctypes.c_double * 12)()
+    M32 = (ctypes.c_float * 12)()
+    _lib.check(_lib.load().ctaug_affine_matrix(ctypes.byref(p), idim, odim, M64, M32),
+               "ctaug_affine_matrix")
+    return np.array(M64[:], dtype=np.float64), np.array(M32[:], dtype=np.float32)
+
+
+def _warp(fn_name, img, M, disp, lbl, fill, label_fill, photo, out_dim, out, lbl_out):
+    _require(img, "img", (torch.float32, torch.int16))
+    if out_dim is None:
+        out_dim = tuple(img.shape) if out is None else tuple(out.shape)
+    if out is None:
+        out = torch.empty(tuple(out_dim), dtype=torch.float32, device=img.device)
+    _require(out, "out", (torch.float32,))
+    if lbl is not None:
+        _require(lbl, "lbl", (torch.int8,))
+        if lbl_out is None:
+            lbl_out = torch.empty(tuple(out.shape), dtype=torch.int8, device=img.device)
+        _require(lbl_out, "lbl_out", (torch.int8,))
+    vi, vo = vol(img), vol(out)
+    vl = vol(lbl) if lbl is not None else None
+    vlo = vol(lbl_out) if lbl is not None else None
+    ph = make_photo(photo)
+    L = _lib.load()
+    args = [ctypes.byref(vi), _ref(vl), _M32(M)]
+    if disp is not None:
+        _require(disp, "disp", (torch.float32,), ndim=4)
+        args.append(ctypes.c_void_p(disp.data_ptr() if disp.numel() else None))
+    st = getattr(L, fn_name)(*args, float(fill), int(label_fill), _ref(ph), ctypes.byref(vo),
+                             _ref(vlo), _stream())
+    _lib.check(st, fn_name)
+    return out, (lbl_out if lbl is not None else None)
+
+
+def warp_affine(img, M, lbl=None, fill=-1000.0, label_fill=0, photo=None, out_dim=None, out=None,
+                lbl_out=None):
+    """Fused affine warp + labels + photometrics.  Returns (out, lbl_out)."""
+    return _warp("ctaug_warp_affine", img, M, None, lbl, fill, label_fill, photo, out_dim, out,
+                 lbl_out)
+
+
+def warp_displacement(img, M, disp, lbl=None, fill=-1000.0, label_fill=0, photo=None,
+                      out=None, lbl_out=None):
+    """As warp_affine with a dense displacement disp [3][Xo][Yo][Zo] added."""
+    out_dim = tuple(disp.shape[1:])
+    return _warp("ctaug_warp_displacement", img, M, disp, lbl, fill, label_fill, photo, out_dim,
+                 out, lbl_out)
+
+
+def photometric_noise(volume, photo):
+    """In-place photometric chain on a float32 volume."""
+    _require(volume, "volume", (torch.float32,))
+    v = vol(volume)
+    ph = make_photo(photo)
+    _lib.check(_lib.load().ctaug_photometric_noise(ctypes.byref(v), ctypes.byref(ph), _stream()),
+               "ctaug_photometric_noise")
+    return volume
+
+
+def noise(seed, volume_id, v0, n, gauss=True, words=False, device="cuda"):
+    """Gaussians n(v) for v in [v0, v0+n) and/or the Philox words of their groups."""
+    g = torch.empty(n, dtype=torch.float32, device=device) if gauss else None
+    ng = ((v0 + n - 1) >> 2) - (v0 >> 2) + 1 if n > 0 else 0
+    w = torch.empty((ng, 4), dtype=torch.int32, device=device) if words else None
+    st = _lib.load().ctaug_noise(int(seed), int(volume_id), int(v0), int(n),
+                                 ctypes.c_void_p(g.data_ptr() if g is not None and n else None),
+                                 ctypes.c_void_p(w.data_ptr() if w is not None and n else None),
+                                 _stream())
+    _lib.check(st, "ctaug_noise")
+    return g, w   # words as int32 bit patterns [groups][4]
+
+
+def warp_backward_workspace(out_dim):
+    d = (ctypes.c_int64 * 3)(*[int(v) for v in out_dim])
+    return int(_lib.load().ctaug_warp_backward_workspace(d))
+
+
+def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp):
+    _require(img, "img", (torch.float32, torch.int16))
+    _require(grad_out, "grad_out", (torch.float32,))
+    dev = img.device
+    g_img = torch.zeros(tuple(img.shape), dtype=torch.float32, device=dev) if want_img else None
+    g_M = torch.empty(12, dtype=torch.float64, device=dev) if want_M else None
+    ws_bytes = warp_backward_workspace(grad_out.shape) if want_M else 0
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if want_M else None
+    vi, vg = vol(img), vol(grad_out)
+    vgi = vol(g_img) if want_img else None
+    L = _lib.load()
+    p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
+    if disp is None:
+        st = L.ctaug_warp_affine_backward(ctypes.byref(vi), _M32(M), float(fill), ctypes.byref(vg),
+                                          _ref(vgi), p(g_M), p(ws), ws_bytes, _stream())
+        _lib.check(st, "ctaug_warp_affine_backward")
+        return g_img, g_M
+    _require(disp, "disp", (torch.float32,), ndim=4)
+    g_disp = torch.empty_like(disp) if want_disp else None
+    st = L.ctaug_warp_displacement_backward(ctypes.byref(vi), _M32(M), p(disp), float(fill),
+                                            ctypes.byref(vg), _ref(vgi), p(g_M), p(g_disp), p(ws),
+                                            ws_bytes, _stream())
+    _lib.check(st, "ctaug_warp_displacement_backward")
+    return g_img, g_M, g_disp
+
+
+def warp_affine_backward(img, M, grad_out, fill=-1000.0, want_img=True, want_M=True):
+    """(grad_img float32 or None, grad_M float64[12] or None)."""
+    return _backward(img, M, grad_out, None, fill, want_img, want_M, False)
+
+
+def warp_displacement_backward(img, M, disp, grad_out, fill=-1000.0, want_img=True,
+                               want_M=True, want_disp=True):
+    """(grad_img, grad_M, grad_disp)."""
+    return _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp)
+
+
+def bspline_upsample(ctrl, out_dim, out=None):
+    """Dense displacement [3][Xo][Yo][Zo] from a control grid [3][Gx][Gy][Gz]."""
+    _require(ctrl, "ctrl", (torch.float32,), ndim=4)
+    if out is None:
+        out = torch.empty((3,) + tuple(int(v) for v in out_dim), dtype=torch.float32,
+                          device=ctrl.device)
+    G = (ctypes.c_int64 * 3)(*ctrl.shape[1:])
+    od = (ctypes.c_int64 * 3)(*[int(v) for v in out_dim])
+    st = _lib.load().ctaug_bspline_upsample(ctypes.c_void_p(ctrl.data_ptr()), G, od,
+                                            ctypes.c_void_p(out.data_ptr() if out.numel() else None),
+                                            _stream())
+    _lib.check(st, "ctaug_bspline_upsample")
+    return out
+
+
+def bspline_upsample_adjoint(grad_disp, grid):
+    _require(grad_disp, "grad_disp", (torch.float32,), ndim=4)
+    G = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    od = (ctypes.c_int64 * 3)(*grad_disp.shape[1:])
+    L = _lib.load()
+    ws_bytes = int(L.ctaug_bspline_adjoint_workspace(od, G))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=grad_disp.device)
+    g = torch.empty((3,) + tuple(int(v) for v in grid), dtype=torch.float32,
+                    device=grad_disp.device)
+    st = L.ctaug_bspline_upsample_adjoint(
+        ctypes.c_void_p(grad_disp.data_ptr() if grad_disp.numel() else None), od, G,
+        ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws_bytes, _stream())
+    _lib.check(st, "ctaug_bspline_upsample_adjoint")
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Batch plan
+# ---------------------------------------------------------------------------
+
+def make_job(img, M, out, lbl=None, lbl_out=None, fill=-1000.0, label_fill=0, photo=None):
+    j = _lib.Job()
+    j.img_in = vol(img)
+    j.img_out = vol(out)
+    if lbl is not None:
+        j.lbl_in = vol(lbl)
+        j.lbl_out = vol(lbl_out)
+    else:
+        j.lbl_in = _lib.Vol()
+        j.lbl_out = _lib.Vol()
+    j.M = _M32(M)
+    j.fill = float(fill)
+    j.label_fill = int(label_fill)
+    ph = make_photo(photo)
+    if ph is None:
+        ph = _lib.Photo()
+        ph.flags = CTAUG_PHOTO_NONE
+        ph.gain, ph.gamma, ph.win_hi = 1.0, 1.0, 1.0
+    j.photo = ph
+    return j
+
+
+class BatchPlan:
+    """One persistent launch over a batch of jobs (device job table, pinned
+    staging, optional HIP graph, autotuned launch shape)."""
+
+    def __init__(self, jobs, tile=None, wg_per_cu=0):
+        self._L = _lib.load()
+        arr = (_lib.Job * len(jobs))(*jobs)
+        tune = None
+        if tile is not None:
+            tune = _lib.Tuning()
+            tune.tile = (ctypes.c_int32 * 3)(*tile)
+            tune.wg_per_cu = wg_per_cu
+        h = ctypes.c_void_p()
+        _lib.check(self._L.ctaug_batch_plan_create(arr, len(jobs), _ref(tune), ctypes.byref(h)),
+                   "ctaug_batch_plan_create")
+        self._h = h
+        self.n = len(jobs)
+
+    def update(self, jobs):
+        arr = (_lib.Job * len(jobs))(*jobs)
+        _lib.check(self._L.ctaug_batch_plan_update(self._h, arr), "ctaug_batch_plan_update")
+
+    def launch(self):
+        _lib.check(self._L.ctaug_batch_plan_launch(self._h, _stream()), "ctaug_batch_plan_launch")
+
+    def capture(self):
+        _lib.check(self._L.ctaug_batch_plan_capture(self._h, _stream()), "ctaug_batch_plan_capture")
+
+    def replay(self):
+        _lib.check(self._L.ctaug_batch_plan_replay(self._h, _stream()), "ctaug_batch_plan_replay")
+
+    def autotune(self, candidates, reps=5):
+        n = len(candidates)
+        cand = (_lib.Tuning * n)()
+        for i, (tile, wg) in enumerate(candidates):
+            cand[i].tile = (ctypes.c_int32 * 3)(*tile)
+            cand[i].wg_per_cu = wg
+        best = _lib.Tuning()
+        times = (ctypes.c_float * n)()
+        _lib.check(self._L.ctaug_batch_plan_autotune(self._h, cand, n, reps, _stream(),
+                                                     ctypes.byref(best), times),
+                   "ctaug_batch_plan_autotune")
+        return (tuple(best.tile), best.wg_per_cu), list(times)
+
+    def tuning(self):
+        t = _lib.Tuning()
+        _lib.check(self._L.ctaug_batch_plan_get_tuning(self._h, ctypes.byref(t)),
+                   "ctaug_batch_plan_get_tuning")
+        return tuple(t.tile), t.wg_per_cu
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ctaug_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

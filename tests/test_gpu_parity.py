@@ -1,0 +1,396 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars: labels and Philox words bit-exact; Box-Muller Gaussians within
+1e-6 * max(1, |n|); intensities within 1e-5 * max(|ref|, R) with R = 1 for
+windowed [0,1] output and R = 1000 HU for HU output; gradients within 1e-4
+normwise per tensor (and elementwise 1e-4 * max(|ref|, 1e-2 ||ref||_inf)).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1811_11226_amd as ctaug
+from synth import AugmentRanges, PhotoParams, configs, draw_affine_params, draw_photo, \
+    identity_affine_params, phantom_pair
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_intensity(got, ref, windowed, what=""):
+    R = 1.0 if windowed else 1000.0
+    err = np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), R)
+    i = int(np.argmax(err)) if err.size else 0
+    assert err.size == 0 or err.max() <= 1e-5, \
+        f"{what}: max scaled error {err.max():.3e} at {np.unravel_index(i, err.shape)}: " \
+        f"got {got.ravel()[i]!r} ref {ref.ravel()[i]!r}"
+
+
+def assert_grad(got, ref, what=""):
+    got = got.astype(np.float64)
+    nref = np.linalg.norm(ref)
+    assert np.linalg.norm(got - ref) <= 1e-4 * max(nref, 1e-30), \
+        f"{what}: normwise {np.linalg.norm(got - ref) / max(nref, 1e-30):.3e}"
+    floor = 1e-2 * np.abs(ref).max() if ref.size else 0.0
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
+    assert err.size == 0 or err.max() <= 1e-4, f"{what}: elementwise {err.max():.3e}"
+
+
+def run_job(job, M=None, out_dim=None, photo="job"):
+    if M is None:
+        _, M = ctaug.affine_matrix(job.prm, job.in_dim, job.out_dim)
+    ph = job.photo if photo == "job" else photo
+    od = job.out_dim if out_dim is None else out_dim
+    img = _t(job.img)
+    lbl = _t(job.lbl) if job.lbl is not None else None
+    out, lout = ctaug.warp_affine(img, M, lbl=lbl, fill=job.fill, label_fill=job.label_fill,
+                                  photo=ph, out_dim=od)
+    ref, lref = oracle.warp(job.img, M, od, lbl=job.lbl, fill=job.fill,
+                            label_fill=job.label_fill, photo=ph)
+    return M, _np(out), (_np(lout) if lout is not None else None), ref, lref
+
+
+# ---------------------------------------------------------------------------
+# Noise: Philox words bit-exact, Gaussians within 1e-6
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,vol,v0,n", [
+    (0, 0, 0, 4096),
+    (20181129, 3, 1, 10001),                      # unaligned start, ragged end
+    (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 34 + 2, 777),  # high counter word in use
+    (123456789, 15, 84 * 2 ** 20 - 5, 1 << 16),
+])
+def test_noise_words_and_gaussians(seed, vol, v0, n):
+    g, w = ctaug.noise(seed, vol, v0, n, gauss=True, words=True)
+    words = _np(w).view(np.uint32)
+    ng = ((v0 + n - 1) >> 2) - (v0 >> 2) + 1
+    ref_w = oracle.noise_words(seed, vol, v0 >> 2, ng)
+    assert np.array_equal(words, ref_w)
+    ref_g = oracle.gauss(seed, vol, v0, n)
+    err = np.abs(_np(g).astype(np.float64) - ref_g) / np.maximum(1.0, np.abs(ref_g))
+    assert err.max() <= 1e-6, f"gaussian error {err.max():.3e}"
+
+
+def test_gaussians_many_samples_within_bound():
+    n = 1 << 22
+    g, _ = ctaug.noise(987654321, 7, 0, n)
+    ref = oracle.gauss(987654321, 7, 0, n)
+    err = np.abs(_np(g).astype(np.float64) - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 1e-6, f"gaussian error {err.max():.3e} at |n|={abs(ref[np.argmax(err)])}"
+
+
+# ---------------------------------------------------------------------------
+# Forward warp: C1 full size, exact invariants, ragged and edge cases
+# ---------------------------------------------------------------------------
+
+def test_c1_full_size_parity():
+    job = configs.c1()[0]
+    _, out, lout, ref, lref = run_job(job)
+    assert np.array_equal(lout, lref)
+    assert_intensity(out, ref, windowed=True, what="c1")
+
+
+def test_c1_hu_output_no_window():
+    job = configs.c1()[0]
+    ph = PhotoParams(**{**job.photo.__dict__, "window": False})
+    _, out, lout, ref, lref = run_job(job, photo=ph)
+    assert np.array_equal(lout, lref)
+    assert_intensity(out, ref, windowed=False, what="c1-hu")
+
+
+def test_identity_and_integer_shift_bit_exact():
+    img, lbl = phantom_pair((37, 29, 23), seed=3)
+    for shift in [(0, 0, 0), (3, -2, 5), (-40, 0, 0)]:
+        M = np.zeros((3, 4), np.float32)
+        M[:, :3] = np.eye(3)
+        M[:, 3] = shift
+        out, lout = ctaug.warp_affine(_t(img), M.ravel(), lbl=_t(lbl), fill=-1000.0)
+        ref, lref = oracle.warp(img, M.ravel(), img.shape, lbl=lbl, fill=-1000.0)
+        assert np.array_equal(_np(out).astype(np.float64), ref)
+        assert np.array_equal(_np(lout), lref)
+
+
+def test_rot90_bit_exact():
+    n = 32
+    img, lbl = phantom_pair((n, n, 20), seed=4)
+    A = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]], np.float64)
+    c = (np.array(img.shape) - 1) / 2
+    M = np.concatenate([A, (c - A @ c)[:, None]], axis=1).astype(np.float32).ravel()
+    out, lout = ctaug.warp_affine(_t(img), M, lbl=_t(lbl))
+    assert np.array_equal(_np(out), np.rot90(img, k=-1, axes=(0, 1)).astype(np.float32))
+    assert np.array_equal(_np(lout), np.rot90(lbl, k=-1, axes=(0, 1)))
+
+
+@pytest.mark.parametrize("in_dim,out_dim,dtype", [
+    ((33, 29, 21), (31, 27, 19), np.float32),     # ragged tiles, Zo % 4 != 0
+    ((40, 36, 30), (17, 9, 7), np.int16),
+    ((96, 101, 130), (120, 120, 160), np.int16),  # crop larger than some axes
+    ((5, 6, 7), (64, 64, 64), np.float32),        # mostly outside
+    ((64, 64, 64), (1, 1, 1), np.float32),
+    ((64, 48, 32), (4, 8, 32), np.int16),         # exactly one tile
+])
+def test_ragged_shapes_parity(in_dim, out_dim, dtype):
+    rng = np.random.default_rng(sum(in_dim) + sum(out_dim))
+    img, lbl = phantom_pair(in_dim, seed=int(rng.integers(1 << 30)))
+    prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+    ph = draw_photo(rng, AugmentRanges(), seed=int(rng.integers(1 << 62)), volume_id=5)
+    job = configs.Job(img=img.astype(dtype), lbl=lbl, out_dim=out_dim, prm=prm, photo=ph)
+    _, out, lout, ref, lref = run_job(job)
+    assert np.array_equal(lout, lref)
+    assert_intensity(out, ref, windowed=True, what=str(out_dim))
+
+
+def test_unaligned_output_pointer_uses_scalar_path():
+    job = configs.c1(dims=(24, 20, 16))[0]
+    _, M = ctaug.affine_matrix(job.prm, job.in_dim, job.out_dim)
+    base = torch.empty(int(np.prod(job.out_dim)) + 1, dtype=torch.float32, device=DEV)
+    out = base[1:].view(job.out_dim)                 # 4-byte but not 16-byte aligned
+    lbase = torch.empty(int(np.prod(job.out_dim)) + 1, dtype=torch.int8, device=DEV)
+    lout = lbase[1:].view(job.out_dim)
+    ctaug.warp_affine(_t(job.img), M, lbl=_t(job.lbl), fill=job.fill, photo=job.photo, out=out,
+                      lbl_out=lout)
+    ref, lref = oracle.warp(job.img, M, job.out_dim, lbl=job.lbl, fill=job.fill, photo=job.photo)
+    assert np.array_equal(_np(lout), lref)
+    assert_intensity(_np(out), ref, windowed=True)
+
+
+def test_no_labels_no_photo():
+    job = configs.c1(dims=(40, 40, 24))[0]
+    _, M = ctaug.affine_matrix(job.prm, job.in_dim, job.out_dim)
+    out, lout = ctaug.warp_affine(_t(job.img), M, fill=job.fill)
+    assert lout is None
+    ref, _ = oracle.warp(job.img, M, job.out_dim, fill=job.fill)
+    assert_intensity(_np(out), ref, windowed=False)
+
+
+def test_empty_volumes_are_noops():
+    img = torch.zeros((0, 4, 4), dtype=torch.float32, device=DEV)
+    out, _ = ctaug.warp_affine(img, np.eye(3, 4).ravel(), fill=7.0, out_dim=(3, 4, 5))
+    assert np.all(_np(out) == 7.0)                   # empty input: everything is fill
+    img = torch.zeros((4, 4, 4), dtype=torch.float32, device=DEV)
+    out, _ = ctaug.warp_affine(img, np.eye(3, 4).ravel(), out_dim=(0, 4, 4))
+    assert out.numel() == 0
+
+
+def test_fused_equals_unfused_bit_exact():
+    job = configs.c1(dims=(64, 48, 40))[0]
+    _, M = ctaug.affine_matrix(job.prm, job.in_dim, job.out_dim)
+    fused, _ = ctaug.warp_affine(_t(job.img), M, fill=job.fill, photo=job.photo)
+    plain, _ = ctaug.warp_affine(_t(job.img), M, fill=job.fill)
+    ctaug.photometric_noise(plain, job.photo)
+    assert torch.equal(fused, plain)
+
+
+def test_photometric_noise_parity():
+    rng = np.random.default_rng(5)
+    v = rng.uniform(-1200, 1500, (30, 17, 11)).astype(np.float32)
+    for window in (True, False):
+        ph = PhotoParams(gain=1.07, offset=-13.0, sigma=12.5, win_lo=-900, win_hi=1100,
+                         gamma=0.85, window=window, seed=42, volume_id=9)
+        t = _t(v)
+        ctaug.photometric_noise(t, ph)
+        ref = oracle.photometric(v.astype(np.float64), ph)
+        assert_intensity(_np(t), ref, windowed=window)
+
+
+def test_repeat_runs_bit_identical():
+    job = configs.c1(dims=(50, 44, 36))[0]
+    _, M = ctaug.affine_matrix(job.prm, job.in_dim, job.out_dim)
+    a, la = ctaug.warp_affine(_t(job.img), M, lbl=_t(job.lbl), photo=job.photo)
+    b, lb = ctaug.warp_affine(_t(job.img), M, lbl=_t(job.lbl), photo=job.photo)
+    assert torch.equal(a, b) and torch.equal(la, lb)
+
+
+# ---------------------------------------------------------------------------
+# Displacement warp and B-spline field
+# ---------------------------------------------------------------------------
+
+def test_displacement_warp_parity_given_field():
+    rng = np.random.default_rng(6)
+    in_dim, out_dim = (40, 36, 28), (38, 34, 24)
+    img, lbl = phantom_pair(in_dim, seed=77)
+    prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    disp = rng.uniform(-3, 3, (3,) + out_dim).astype(np.float32)
+    ph = draw_photo(rng, AugmentRanges(), seed=99, volume_id=1)
+    out, lout = ctaug.warp_displacement(_t(img.astype(np.float32)), M, _t(disp), lbl=_t(lbl),
+                                        photo=ph)
+    ref, lref = oracle.warp(img, M, out_dim, lbl=lbl, disp=disp, photo=ph)
+    assert np.array_equal(_np(lout), lref)
+    assert_intensity(_np(out), ref, windowed=True)
+
+
+@pytest.mark.parametrize("out_dim,grid", [((64, 48, 40), (8, 8, 8)), ((33, 17, 9), (6, 5, 7)),
+                                          ((1, 12, 16), (4, 4, 4))])
+def test_bspline_upsample_parity(out_dim, grid):
+    rng = np.random.default_rng(7)
+    C = (4.0 * rng.standard_normal((3,) + grid)).astype(np.float32)
+    u = ctaug.bspline_upsample(_t(C), out_dim)
+    ref = oracle.bspline_upsample(C, out_dim)
+    err = np.abs(_np(u).astype(np.float64) - ref).max()
+    assert err <= 1e-5 * np.abs(C).max(), err
+
+
+@pytest.mark.parametrize("out_dim,grid", [((64, 48, 40), (8, 8, 8)), ((70, 130, 9), (6, 9, 7))])
+def test_bspline_adjoint_parity(out_dim, grid):
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal((3,) + out_dim).astype(np.float32)
+    gc = ctaug.bspline_upsample_adjoint(_t(g), grid)
+    ref = oracle.bspline_adjoint(g.astype(np.float64), grid)
+    assert_grad(_np(gc), ref, "g_ctrl")
+
+
+# ---------------------------------------------------------------------------
+# Backward
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims,dtype", [((48, 40, 36), np.float32), ((33, 29, 21), np.int16)])
+def test_affine_backward_parity(dims, dtype):
+    rng = np.random.default_rng(9)
+    img, _ = phantom_pair(dims, seed=5)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    g = rng.standard_normal(dims).astype(np.float32)
+    g_img, g_M = ctaug.warp_affine_backward(_t(img.astype(dtype)), M, _t(g))
+    r_img, r_M, _ = oracle.warp_backward(img, M, g)
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
+
+
+def test_affine_backward_adjoint_identity_gpu():
+    rng = np.random.default_rng(10)
+    dims = (40, 40, 40)
+    x = rng.standard_normal(dims).astype(np.float32)
+    y = rng.standard_normal(dims).astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    Wx, _ = ctaug.warp_affine(_t(x), M, fill=0.0)
+    WTy, _ = ctaug.warp_affine_backward(_t(x), M, _t(y), fill=0.0, want_M=False)
+    Wx, WTy = _np(Wx).astype(np.float64), _np(WTy).astype(np.float64)
+    lhs, rhs = np.vdot(Wx, y), np.vdot(x, WTy)
+    # Higham: |fl(<a,b>) - <a,b>| <= gamma_k |a|^T |b|, k = accumulation chain length
+    u = 2.0 ** -24
+    k = 64     # upper bound on terms accumulated into one element
+    bound = (k * u / (1 - k * u)) * (np.abs(Wx).ravel() @ np.abs(y).ravel() +
+                                     np.abs(x).ravel() @ np.abs(WTy).ravel())
+    assert abs(lhs - rhs) <= bound
+
+
+def test_displacement_backward_parity():
+    rng = np.random.default_rng(11)
+    dims = (36, 32, 28)
+    img, _ = phantom_pair(dims, seed=8)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    disp = rng.uniform(-2, 2, (3,) + dims).astype(np.float32)
+    g = rng.standard_normal(dims).astype(np.float32)
+    g_img, g_M, g_disp = ctaug.warp_displacement_backward(_t(img.astype(np.float32)), M, _t(disp),
+                                                          _t(g))
+    r_img, r_M, r_u = oracle.warp_backward(img, M, g, disp=disp, want_u=True)
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
+    assert_grad(_np(g_disp), r_u, "g_disp")
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent launch and HIP graph replay
+# ---------------------------------------------------------------------------
+
+def _batch_jobs(n=4, out_dim=(40, 40, 48), size_range=(30, 64)):
+    jobs = configs.c3(n=n, size_range=size_range, out_dim=out_dim)
+    tensors = []
+    for j in jobs:
+        _, M = ctaug.affine_matrix(j.prm, j.in_dim, j.out_dim)
+        img, lbl = _t(j.img), _t(j.lbl)
+        out = torch.empty(out_dim, dtype=torch.float32, device=DEV)
+        lout = torch.empty(out_dim, dtype=torch.int8, device=DEV)
+        tensors.append((j, M, img, lbl, out, lout))
+    return tensors
+
+
+def test_batch_plan_matches_single_calls_and_oracle():
+    T = _batch_jobs()
+    jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
+            for (j, M, img, lbl, out, lout) in T]
+    plan = ctaug.BatchPlan(jobs)
+    plan.launch()
+    for (j, M, img, lbl, out, lout) in T:
+        s_out, s_lout = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo,
+                                          out_dim=j.out_dim)
+        assert torch.equal(out, s_out) and torch.equal(lout, s_lout)
+        ref, lref = oracle.warp(j.img, M, j.out_dim, lbl=j.lbl, fill=j.fill, photo=j.photo)
+        assert np.array_equal(_np(lout), lref)
+        assert_intensity(_np(out), ref, windowed=True)
+    plan.close()
+
+
+@pytest.mark.parametrize("tile,wg", [((4, 8, 32), 0), ((8, 8, 16), 2), ((2, 4, 64), 1),
+                                     ((16, 16, 16), 4)])
+def test_batch_launch_shapes_bit_identical(tile, wg):
+    T = _batch_jobs(n=3, out_dim=(36, 30, 44))
+    jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
+            for (j, M, img, lbl, out, lout) in T]
+    plan = ctaug.BatchPlan(jobs, tile=tile, wg_per_cu=wg)
+    plan.launch()
+    for (j, M, img, lbl, out, lout) in T:
+        s_out, s_lout = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo,
+                                          out_dim=j.out_dim)
+        assert torch.equal(out, s_out) and torch.equal(lout, s_lout)
+    plan.close()
+
+
+def test_batch_graph_replay_with_updates():
+    T = _batch_jobs(n=3)
+    jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
+            for (j, M, img, lbl, out, lout) in T]
+    plan = ctaug.BatchPlan(jobs)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture()
+    rng = np.random.default_rng(12)
+    for rep in range(4):
+        # new transforms and photometrics each replay, no re-capture
+        newT, new_jobs = [], []
+        for (j, M, img, lbl, out, lout) in T:
+            prm = draw_affine_params(rng, AugmentRanges(), j.in_dim, j.out_dim)
+            _, M2 = ctaug.affine_matrix(prm, j.in_dim, j.out_dim)
+            ph = draw_photo(rng, AugmentRanges(), seed=1000 + rep, volume_id=j.volume_id)
+            newT.append((j, M2, ph, img, lbl, out, lout))
+            new_jobs.append(ctaug.make_job(img, M2, out, lbl, lout, fill=j.fill, photo=ph))
+        plan.update(new_jobs)
+        with torch.cuda.stream(stream):
+            plan.replay()
+        stream.synchronize()
+        for (j, M2, ph, img, lbl, out, lout) in newT:
+            s_out, s_lout = ctaug.warp_affine(img, M2, lbl=lbl, fill=j.fill, photo=ph,
+                                              out_dim=j.out_dim)
+            assert torch.equal(out, s_out) and torch.equal(lout, s_lout), f"replay {rep}"
+    plan.close()
+
+
+def test_autotune_picks_a_candidate_and_results_hold():
+    T = _batch_jobs(n=2)
+    jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
+            for (j, M, img, lbl, out, lout) in T]
+    plan = ctaug.BatchPlan(jobs)
+    cands = [((4, 8, 32), 0), ((8, 8, 16), 0), ((4, 8, 32), 4)]
+    best, times = plan.autotune(cands, reps=2)
+    assert best in cands and all(t > 0 for t in times)
+    assert plan.tuning() == best
+    plan.launch()
+    for (j, M, img, lbl, out, lout) in T:
+        s_out, _ = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo,
+                                     out_dim=j.out_dim)
+        assert torch.equal(out, s_out)
+    plan.close()
