@@ -184,6 +184,13 @@ ctaug_status ctaug_photometric_noise(ctaug_vol *inout, const ctaug_photo *photo,
 ctaug_status ctaug_noise(uint64_t seed, uint32_t volume_id, uint64_t v0, int64_t n,
                          float *gauss, uint32_t *words, void *stream);
 
+/* The Box-Muller step of ctaug_noise on caller-supplied words: for pair i,
+ * out[2i] = r cos(theta), out[2i+1] = r sin(theta) with r = sqrt(-2 ln U(w[2i])),
+ * theta = 2 pi U(w[2i+1]).  words, out: device arrays of 2*npairs elements.
+ * Lets callers check or reuse the normal transform on any uniform input.
+ * Errors: EINVAL (npairs < 0, null pointer with npairs > 0), EHIP. */
+ctaug_status ctaug_box_muller(const uint32_t *words, int64_t npairs, float *out, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Adjoints (not in the paper)                                               */
 /* ------------------------------------------------------------------------ */
@@ -260,12 +267,21 @@ typedef struct {
 
 #define CTAUG_PHOTO_NONE 0x80000000u
 
-/* Launch shape: output tile (voxels along x, y, z; z a multiple of 4), and
- * the number of resident workgroups per CU for the persistent launch
- * (0 = one workgroup per tile, non-persistent). */
+/* Launch shape: output tile (voxels along x, y, z; each a power of two, z at
+ * least 4, at most 2^14 voxels), the number of resident workgroups per CU for
+ * the persistent launch (0 = one workgroup per tile, non-persistent), and the
+ * LDS footprint reserved per workgroup in input cells (0 = sized from the
+ * jobs; -1 = no LDS staging), and the cell format: 0 = FP32 cells (5 bytes
+ * per cell with the int8 label; at most 12272 cells in the 60 KB
+ * reservation), 1 = int16 cells when every input is int16 (3 bytes per cell,
+ * at most 20464 cells; half the LDS, more LDS reads).  Tiles whose footprint
+ * exceeds the reservation, and int16-cell jobs whose fill value is not an
+ * int16, gather directly from global memory, with identical results. */
 typedef struct {
     int32_t tile[3];
     int32_t wg_per_cu;
+    int32_t lds_cells;
+    int32_t lds_format;
 } ctaug_tuning;
 
 typedef struct ctaug_batch_plan ctaug_batch_plan;
@@ -278,7 +294,8 @@ ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n_jobs,
                                      const ctaug_tuning *tune, ctaug_batch_plan **plan);
 
 /* Replace the jobs' contents (pointers, matrices, photometrics).  Every job
- * must keep the output dims it had at plan creation.  Waits (host side) for
+ * must keep the output dims it had at plan creation (else ESHAPE), and an
+ * FP32 input is refused (EDTYPE) in a plan created with only int16 inputs.  Waits (host side) for
  * the previous launch's table upload to finish before overwriting staging. */
 ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jobs);
 
@@ -286,6 +303,11 @@ ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jo
  * persistent launch that warps every job.  Results equal ctaug_warp_affine
  * on each job, bit for bit. */
 ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *plan, void *stream);
+
+/* Enqueue only the persistent launch, reading the job table uploaded by the
+ * last launch/replay (no upload): re-runs the same descriptors, e.g. after the
+ * caller refilled the same input buffers in place. */
+ctaug_status ctaug_batch_plan_run(ctaug_batch_plan *plan, void *stream);
 
 /* Capture ctaug_batch_plan_launch on `stream` into a HIP graph owned by the
  * plan (replacing any earlier one); ctaug_batch_plan_replay then launches it.
@@ -305,6 +327,16 @@ ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *plan, const ctaug_tunin
 
 ctaug_status ctaug_batch_plan_get_tuning(const ctaug_batch_plan *plan, ctaug_tuning *out);
 ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *plan);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement helper                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Plain device-to-device copy of `bytes` bytes by a streaming kernel (16-byte
+ * vector loads and stores when both pointers are 16-byte aligned).  Used as the
+ * reference kernel of known traffic when scaling hardware byte counters, and
+ * to evict the Infinity Cache between timed runs.  Errors: EINVAL, EHIP. */
+ctaug_status ctaug_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,8 @@ def _declare(L):
     L.orc_uniform.restype = _dbl
     L.orc_gauss.argtypes = [_u64, _u32, _u64]
     L.orc_gauss.restype = _dbl
+    L.orc_box_muller.argtypes = [_p, _i64, _p]
+    L.orc_box_muller.restype = None
     L.orc_gauss_range.argtypes = [_u64, _u32, _u64, _i64, _p]
     L.orc_gauss_range.restype = None
     L.orc_photometric.argtypes = [_p, _i64, _p, _int, _u64, _u32, _p]
@@ -111,6 +113,13 @@ def uniform(w):
 def gauss(seed, vol, v0, n):
     out = np.zeros(n, dtype=np.float64)
     lib().orc_gauss_range(seed, vol, v0, n, _ptr(out))
+    return out
+
+
+def box_muller(words):
+    w = np.ascontiguousarray(words, dtype=np.uint32).ravel()
+    out = np.empty(w.size, dtype=np.float64)
+    lib().orc_box_muller(_ptr(w), w.size // 2, _ptr(out))
     return out
 
 

@@ -123,6 +123,17 @@ double orc_gauss(uint64_t seed, uint32_t vol, uint64_t v)
     return (v & 1u) ? r * sin(theta) : r * cos(theta);
 }
 
+/* Box-Muller on explicit words: out[2i] = r cos(theta), out[2i+1] = r sin(theta). */
+void orc_box_muller(const uint32_t *w, int64_t npairs, double *out)
+{
+    for (int64_t i = 0; i < npairs; ++i) {
+        double r = sqrt(-2.0 * log(orc_uniform(w[2 * i])));
+        double theta = 2.0 * M_PI * orc_uniform(w[2 * i + 1]);
+        out[2 * i] = r * cos(theta);
+        out[2 * i + 1] = r * sin(theta);
+    }
+}
+
 void orc_gauss_range(uint64_t seed, uint32_t vol, uint64_t v0, int64_t n, double *out)
 {
     for (int64_t i = 0; i < n; ++i)

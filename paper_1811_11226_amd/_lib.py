@@ -49,7 +49,8 @@ class Job(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32 * 3), ("wg_per_cu", ctypes.c_int32)]
+    _fields_ = [("tile", ctypes.c_int32 * 3), ("wg_per_cu", ctypes.c_int32),
+                ("lds_cells", ctypes.c_int32), ("lds_format", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -71,6 +72,7 @@ SIGNATURES = {
     "ctaug_photometric_noise": (_S, [_PV, ctypes.POINTER(Photo), _P]),
     "ctaug_noise": (_S, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, _P,
                          _P, _P]),
+    "ctaug_box_muller": (_S, [_P, ctypes.c_int64, _P, _P]),
     "ctaug_warp_backward_workspace": (ctypes.c_size_t, [_PI64]),
     "ctaug_warp_affine_backward": (_S, [_PV, _PF, ctypes.c_float, _PV, _PV, _P, _P,
                                         ctypes.c_size_t, _P]),
@@ -83,12 +85,14 @@ SIGNATURES = {
                                      ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_void_p)]),
     "ctaug_batch_plan_update": (_S, [_P, ctypes.POINTER(Job)]),
     "ctaug_batch_plan_launch": (_S, [_P, _P]),
+    "ctaug_batch_plan_run": (_S, [_P, _P]),
     "ctaug_batch_plan_capture": (_S, [_P, _P]),
     "ctaug_batch_plan_replay": (_S, [_P, _P]),
     "ctaug_batch_plan_autotune": (_S, [_P, ctypes.POINTER(Tuning), ctypes.c_int32, ctypes.c_int32,
                                        _P, ctypes.POINTER(Tuning), _PF]),
     "ctaug_batch_plan_get_tuning": (_S, [_P, ctypes.POINTER(Tuning)]),
     "ctaug_batch_plan_destroy": (_S, [_P]),
+    "ctaug_copy": (_S, [_P, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None

@@ -2,6 +2,7 @@
 // descriptor construction, launch configuration and the batch plan
 // (device job table + pinned staging + HIP graph + autotuner).
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -15,7 +16,7 @@ using namespace ctaug;
 namespace {
 
 constexpr int64_t kMaxElems = 2147483647LL;   // int32 linear indices in the kernels
-constexpr Tiling kDefaultTiling = {2, 3, 5};   // 4 x 8 x 32 output voxels per workgroup
+constexpr Tiling kDefaultTiling = {3, 4, 4};   // 8 x 16 x 16 output voxels per workgroup
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -187,6 +188,8 @@ ctaug_status make_job(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const fl
     }
     J.fill = fill;
     J.label_fill = label_fill;
+    if (fill >= -32768.0f && fill <= 32767.0f && (float)(int16_t)fill == fill)
+        J.flags |= kFlagFillInT;
     if (J.lbl)
         J.flags |= kFlagLabels;
     set_photo(J, photo);
@@ -347,6 +350,16 @@ extern "C" ctaug_status ctaug_noise(uint64_t seed, uint32_t volume_id, uint64_t 
                                    words, as_stream(stream)));
 }
 
+extern "C" ctaug_status ctaug_box_muller(const uint32_t *words, int64_t npairs, float *out,
+                                         void *stream)
+{
+    if (npairs < 0 || (npairs > 0 && (!words || !out)))
+        return CTAUG_EINVAL;
+    if (npairs == 0)
+        return CTAUG_OK;
+    return hip_status(launch_box_muller(words, npairs, out, as_stream(stream)));
+}
+
 extern "C" size_t ctaug_warp_backward_workspace(const int64_t out_dim[3])
 {
     if (!out_dim || !dims_valid(out_dim))
@@ -478,6 +491,10 @@ struct ctaug_batch_plan {
     ctaug_tuning tune{};
     Tiling TL = kDefaultTiling;
     int32_t grid = 0;
+    int32_t lds_cells = 0;              // LDS footprint cells reserved per workgroup
+    int32_t elem_bytes = 4;             // LDS cell width: 2 when int16 cells are used
+    bool all_i16 = true;                // every job has an int16 input
+    bool aligned = true;                // every job's output z extent is a multiple of 4
     int num_cu = 256;
     hipEvent_t upload_done = nullptr;
     bool upload_recorded = false;
@@ -501,7 +518,9 @@ ctaug_status tiling_of(const ctaug_tuning *t, Tiling &TL)
         return CTAUG_OK;
     }
     const int lx = ilog2(t->tile[0]), ly = ilog2(t->tile[1]), lz = ilog2(t->tile[2]);
-    if (lx < 0 || ly < 0 || lz < 2 || lx + ly + lz > 14 || t->wg_per_cu < 0 || t->wg_per_cu > 32)
+    if (lx < 0 || ly < 0 || lz < 2 || lx + ly + lz > 14 || t->wg_per_cu < 0 || t->wg_per_cu > 32 ||
+        t->lds_cells < -1 || t->lds_cells > lds_cells_cap(2) || t->lds_format < 0 ||
+        t->lds_format > 1)
         return CTAUG_EINVAL;
     TL = {lx, ly, lz};
     return CTAUG_OK;
@@ -534,14 +553,31 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
         return st;
     std::vector<int32_t> prefix(p->n + 1, 0);
     int64_t total = 0;
+    p->elem_bytes = (t.lds_format == 1 && p->all_i16) ? 2 : 4;
     for (int i = 0; i < p->n; ++i) {
         set_tiles(p->jobs[i], TL);
+        if (p->elem_bytes == 2)
+            p->jobs[i].flags |= kFlagLds16;
+        else
+            p->jobs[i].flags &= ~kFlagLds16;
         prefix[i] = (int32_t)total;
         total += (int64_t)p->jobs[i].tiles_x * p->jobs[i].tiles_y * p->jobs[i].tiles_z;
     }
     if (total > (int64_t)kMaxElems)
         return CTAUG_ESHAPE;
     prefix[p->n] = (int32_t)total;
+    int32_t cells = t.lds_cells < 0 ? 0 : t.lds_cells;
+    if (t.lds_cells == 0) {
+        // the largest footprint of the current jobs, with headroom for later
+        // updates; tiles that still exceed it take the direct-gather path
+        int64_t need = 0;
+        for (int i = 0; i < p->n; ++i)
+            need = std::max<int64_t>(need, footprint_cells_bound(p->jobs[i], TL));
+        cells = lds_cells_for((int32_t)std::min<int64_t>(need + need / 4 + 64, 1 << 20),
+                              p->elem_bytes);
+    } else if (cells > lds_cells_cap(p->elem_bytes)) {
+        return CTAUG_EINVAL;
+    }
     if (hipMemcpy(p->prefix_dev, prefix.data(), sizeof(int32_t) * (p->n + 1),
                   hipMemcpyHostToDevice) != hipSuccess)
         return CTAUG_EHIP;
@@ -550,6 +586,8 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
     p->TL = TL;
     p->tune = t;
+    p->tune.lds_cells = t.lds_cells < 0 ? -1 : cells;
+    p->lds_cells = cells;
     p->total = (int32_t)total;
     const int64_t tiles8 = ((total + 7) / 8) * 8;
     int64_t grid = t.wg_per_cu > 0 ? (int64_t)p->num_cu * t.wg_per_cu : tiles8;
@@ -564,7 +602,9 @@ ctaug_status enqueue(ctaug_batch_plan *p, hipStream_t s)
     if (hipMemcpyAsync(p->table, p->staging, sizeof(FwdJob) * p->n, hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return CTAUG_EHIP;
-    return hip_status(launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL, s));
+    return hip_status(
+        launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL, p->lds_cells,
+                          p->elem_bytes, p->aligned, s));
 }
 
 }  // namespace
@@ -610,6 +650,9 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
         p->out_dims[3 * i + 0] = p->jobs[i].ox;
         p->out_dims[3 * i + 1] = p->jobs[i].oy;
         p->out_dims[3 * i + 2] = p->jobs[i].oz;
+        p->aligned = p->aligned && p->jobs[i].oz % 4 == 0;
+        if (p->jobs[i].dtype != CTAUG_I16)
+            p->all_i16 = false;
     }
     int dev = 0;
     hipDeviceProp_t prop;
@@ -627,7 +670,7 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
         ctaug_batch_plan_destroy(p);
         return CTAUG_EHIP;
     }
-    ctaug_tuning t = tune ? *tune : ctaug_tuning{{4, 8, 32}, 0};
+    ctaug_tuning t = tune ? *tune : ctaug_tuning{{8, 16, 16}, 0, 0, 0};
     st = apply_tiling(p, t);
     if (st != CTAUG_OK) {
         ctaug_batch_plan_destroy(p);
@@ -649,9 +692,14 @@ extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug
         if (next[i].ox != p->out_dims[3 * i] || next[i].oy != p->out_dims[3 * i + 1] ||
             next[i].oz != p->out_dims[3 * i + 2])
             return CTAUG_ESHAPE;
+        if (next[i].dtype != CTAUG_I16 && p->elem_bytes < 4)
+            return CTAUG_EDTYPE;           // the LDS reservation was sized for int16 cells
     }
     if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
         return CTAUG_EHIP;
+    for (int i = 0; i < p->n; ++i)
+        if (p->elem_bytes == 2)
+            next[i].flags |= kFlagLds16;
     p->jobs = next;
     std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
     return CTAUG_OK;
@@ -669,6 +717,24 @@ extern "C" ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *p, void *strea
         return CTAUG_EHIP;
     p->upload_recorded = true;
     return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_run(ctaug_batch_plan *p, void *stream)
+{
+    if (!p || !p->upload_recorded)
+        return CTAUG_EINVAL;
+    return hip_status(launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL,
+                                        p->lds_cells, p->elem_bytes, p->aligned,
+                                        as_stream(stream)));
+}
+
+extern "C" ctaug_status ctaug_copy(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (bytes == 0)
+        return CTAUG_OK;
+    if (!src || !dst)
+        return CTAUG_EINVAL;
+    return hip_status(launch_copy(src, dst, bytes, as_stream(stream)));
 }
 
 extern "C" ctaug_status ctaug_batch_plan_capture(ctaug_batch_plan *p, void *stream)

@@ -14,6 +14,7 @@ namespace ctaug {
 
 constexpr int kThreads = 256;          // workgroup size of every warp kernel
 constexpr int kRun = 4;                // output voxels per thread along z
+constexpr int kMaxLdsBytes = 61440;    // LDS footprint reservation per workgroup (60 KB)
 
 enum : uint32_t {
     kFlagWindow = 1u,                  // window + gamma
@@ -22,6 +23,8 @@ enum : uint32_t {
     kFlagNoise = 8u,                   // sigma > 0
     kFlagGamma = 16u,                  // gamma != 1
     kFlagVec = 32u,                    // 16-byte aligned outputs, Zo % 4 == 0
+    kFlagFillInT = 64u,                // fill is exactly representable as an int16
+    kFlagLds16 = 128u,                 // int16 input staged as int16 LDS cells
 };
 
 enum : int32_t { kF32 = 0, kI16 = 1, kI8 = 2 };
@@ -70,14 +73,73 @@ __device__ __forceinline__ float coord(const float *M, int i, const float r[3], 
 }
 
 // ---------------------------------------------------------------------------
-// Input element loads
+// Global-memory pointer types.  Pointers read from a job table are generic to
+// the compiler; casting them to the global address space gives global_load /
+// global_store with an SGPR base and a 32-bit VGPR offset instead of flat
+// accesses.
 // ---------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ float ld(const T *p, int32_t i);
-template <> __device__ __forceinline__ float ld<float>(const float *p, int32_t i) { return p[i]; }
-template <> __device__ __forceinline__ float ld<int16_t>(const int16_t *p, int32_t i)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <typename T> using gconst = __attribute__((address_space(1))) const T;
+template <typename T> using gmut = __attribute__((address_space(1))) T;
+
+template <typename T> __device__ __forceinline__ gconst<T> *gc(const void *p)
 {
-    return (float)p[i];
+    return (gconst<T> *)p;
 }
+template <typename T> __device__ __forceinline__ gmut<T> *gm(void *p) { return (gmut<T> *)p; }
+
+// ---------------------------------------------------------------------------
+// Buffer resources.  Input gathers use raw buffer loads: an SGPR descriptor
+// with the base and byte size, a 32-bit VGPR byte offset, an optional SGPR
+// offset and a 12-bit immediate.  Every load is kept inside the volume (the
+// compiler may merge loads at adjacent offsets into one wider load, whose
+// range check would then also cover the in-range neighbour), so corners that
+// will be replaced by the fill value are loaded from clamped indices.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRawBufferFlags = 0x00020000;   // raw (unformatted) dword buffer, gfx9 encoding
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             kRawBufferFlags);
+}
+
+template <typename T> struct Elem;
+template <> struct Elem<float> {
+    static __device__ __forceinline__ float raw(rsrc_t r, uint32_t off, int32_t soff)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    }
+    static __device__ __forceinline__ float load(rsrc_t r, uint32_t off, int32_t soff)
+    {
+        return raw(r, off, soff);
+    }
+};
+template <> struct Elem<int16_t> {
+    static __device__ __forceinline__ int16_t raw(rsrc_t r, uint32_t off, int32_t soff)
+    {
+        return (int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+    }
+    static __device__ __forceinline__ float load(rsrc_t r, uint32_t off, int32_t soff)
+    {
+        return (float)raw(r, off, soff);
+    }
+};
+
+// Offset of the label array in a footprint reservation of `cells` cells of T.
+template <typename T> __device__ __host__ __forceinline__ uint32_t lds_label_offset(int32_t cells)
+{
+    return ((uint32_t)cells * (uint32_t)sizeof(T) + 15u) & ~15u;
+}
+
+__device__ __forceinline__ int8_t load_i8(rsrc_t r, uint32_t off)
+{
+    return (int8_t)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+
+// 24-bit multiply (full rate); operands and product must stay below 2^24 / 2^32.
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return __umul24(a, b); }
 
 __device__ __forceinline__ float lerp(float a, float b, float t)
 {
@@ -92,25 +154,54 @@ __device__ __forceinline__ float tri(const float k[8], float tx, float ty, float
     return lerp(lerp(e00, e01, ty), lerp(e10, e11, ty), tx);
 }
 
-// Sample whose cell [i0, i0+1]^3 is known to lie inside the volume.
+// Input volume geometry for gathers: dims, byte strides between x / y
+// neighbours, and the buffer resources of image and labels.
+struct Src {
+    rsrc_t img, lbl;
+    int32_t nx, ny, nz;
+    int32_t sy, sx, sxy;               // byte offsets of the +y, +x, +x+y corner rows
+};
+
 template <typename T>
-__device__ __forceinline__ float sample_interior(const T *img, int32_t ny, int32_t nz, float qx,
-                                                 float qy, float qz)
+__device__ __forceinline__ Src make_src(const void *img, const int8_t *lbl, int32_t nx, int32_t ny,
+                                        int32_t nz)
 {
-    float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-    float tx = qx - fx, ty = qy - fy, tz = qz - fz;
-    int32_t base = ((int32_t)fx * ny + (int32_t)fy) * nz + (int32_t)fz;
-    int32_t sy = nz, sx = ny * nz;
+    Src S;
+    const uint32_t n = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
+    S.img = make_rsrc(img, n * (uint32_t)sizeof(T));
+    S.lbl = make_rsrc(lbl, lbl ? n : 0u);
+    S.nx = nx;
+    S.ny = ny;
+    S.nz = nz;
+    S.sy = nz * (int32_t)sizeof(T);
+    S.sx = ny * nz * (int32_t)sizeof(T);
+    S.sxy = S.sx + S.sy;
+    return S;
+}
+
+__device__ __forceinline__ uint32_t elem_index(const Src &S, int32_t ix, int32_t iy, int32_t iz)
+{
+    return mul24(mul24((uint32_t)ix, (uint32_t)S.ny) + (uint32_t)iy, (uint32_t)S.nz) + (uint32_t)iz;
+}
+
+// Sample whose cell [i0, i0+1]^3 is known to lie inside the volume: one VGPR
+// offset, the other corner rows through SGPR offsets and the immediate.
+template <typename T>
+__device__ __forceinline__ float sample_interior(const Src &S, float qx, float qy, float qz)
+{
+    const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+    const uint32_t off = elem_index(S, (int32_t)fx, (int32_t)fy, (int32_t)fz) * (uint32_t)sizeof(T);
+    constexpr uint32_t e = sizeof(T);
     float k[8];
-    k[0] = ld(img, base);
-    k[1] = ld(img, base + 1);
-    k[2] = ld(img, base + sy);
-    k[3] = ld(img, base + sy + 1);
-    k[4] = ld(img, base + sx);
-    k[5] = ld(img, base + sx + 1);
-    k[6] = ld(img, base + sx + sy);
-    k[7] = ld(img, base + sx + sy + 1);
-    return tri(k, tx, ty, tz);
+    k[0] = Elem<T>::load(S.img, off, 0);
+    k[1] = Elem<T>::load(S.img, off + e, 0);
+    k[2] = Elem<T>::load(S.img, off, S.sy);
+    k[3] = Elem<T>::load(S.img, off + e, S.sy);
+    k[4] = Elem<T>::load(S.img, off, S.sx);
+    k[5] = Elem<T>::load(S.img, off + e, S.sx);
+    k[6] = Elem<T>::load(S.img, off, S.sxy);
+    k[7] = Elem<T>::load(S.img, off + e, S.sxy);
+    return tri(k, qx - fx, qy - fy, qz - fz);
 }
 
 __device__ __forceinline__ bool in_guard(float qx, float qy, float qz, int32_t nx, int32_t ny,
@@ -121,71 +212,70 @@ __device__ __forceinline__ bool in_guard(float qx, float qy, float qz, int32_t n
 }
 
 // Corners of the cell floor(q) with `fill` for every corner outside the
-// volume.  Requires in_guard(q).  Addresses are clamped so every load is in
-// bounds; the clamped value is then replaced by fill.
+// volume.  Requires in_guard(q).  Out-of-volume corners are loaded from the
+// clamped index and then replaced by fill.
 template <typename T>
-__device__ __forceinline__ void corners_checked(const T *img, int32_t nx, int32_t ny, int32_t nz,
-                                                float qx, float qy, float qz, float fill,
-                                                float k[8], float t[3], int32_t i0[3])
+__device__ __forceinline__ void corners_checked(const Src &S, float qx, float qy, float qz,
+                                                float fill, float k[8], float t[3],
+                                                int32_t i0[3])
 {
-    float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+    const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
     t[0] = qx - fx;
     t[1] = qy - fy;
     t[2] = qz - fz;
-    int32_t ix = (int32_t)fx, iy = (int32_t)fy, iz = (int32_t)fz;
+    const int32_t ix = (int32_t)fx, iy = (int32_t)fy, iz = (int32_t)fz;
     i0[0] = ix;
     i0[1] = iy;
     i0[2] = iz;
-    bool vx[2] = {ix >= 0, ix + 1 < nx};
-    bool vy[2] = {iy >= 0, iy + 1 < ny};
-    bool vz[2] = {iz >= 0, iz + 1 < nz};
-    int32_t cx[2] = {max(ix, 0), min(ix + 1, nx - 1)};
-    int32_t cy[2] = {max(iy, 0), min(iy + 1, ny - 1)};
-    int32_t cz[2] = {max(iz, 0), min(iz + 1, nz - 1)};
+    const bool vx[2] = {ix >= 0, ix + 1 < S.nx};
+    const bool vy[2] = {iy >= 0, iy + 1 < S.ny};
+    const bool vz[2] = {iz >= 0, iz + 1 < S.nz};
+    const int32_t cx[2] = {max(ix, 0), min(ix + 1, S.nx - 1)};
+    const int32_t cy[2] = {max(iy, 0), min(iy + 1, S.ny - 1)};
+    const int32_t cz[2] = {max(iz, 0), min(iz + 1, S.nz - 1)};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                float v = ld(img, (cx[a] * ny + cy[b]) * nz + cz[c]);
+                const uint32_t off = elem_index(S, cx[a], cy[b], cz[c]) * (uint32_t)sizeof(T);
+                const float v = Elem<T>::load(S.img, off, 0);
                 k[4 * a + 2 * b + c] = (vx[a] && vy[b] && vz[c]) ? v : fill;
             }
 }
 
 template <typename T>
-__device__ __forceinline__ float sample_checked(const T *img, int32_t nx, int32_t ny, int32_t nz,
-                                                float qx, float qy, float qz, float fill)
+__device__ __forceinline__ float sample_checked(const Src &S, float qx, float qy, float qz,
+                                                float fill)
 {
-    if (!in_guard(qx, qy, qz, nx, ny, nz))
+    if (!in_guard(qx, qy, qz, S.nx, S.ny, S.nz))
         return fill;
     float k[8], t[3];
     int32_t i0[3];
-    corners_checked(img, nx, ny, nz, qx, qy, qz, fill, k, t, i0);
+    corners_checked<T>(S, qx, qy, qz, fill, k, t, i0);
     return tri(k, t[0], t[1], t[2]);
 }
 
 // Nearest label: j = floorf(q + 0.5f) per axis (FP32, ties up).
 __device__ __forceinline__ int32_t nn_index(float q) { return (int32_t)floorf(q + 0.5f); }
 
-__device__ __forceinline__ int8_t label_checked(const int8_t *lbl, int32_t nx, int32_t ny,
-                                                int32_t nz, float qx, float qy, float qz,
+__device__ __forceinline__ int8_t label_checked(const Src &S, float qx, float qy, float qz,
                                                 int8_t label_fill)
 {
-    if (!in_guard(qx, qy, qz, nx, ny, nz))
+    if (!in_guard(qx, qy, qz, S.nx, S.ny, S.nz))
         return label_fill;
-    int32_t jx = nn_index(qx), jy = nn_index(qy), jz = nn_index(qz);
-    bool ok = jx >= 0 && jx < nx && jy >= 0 && jy < ny && jz >= 0 && jz < nz;
-    int32_t idx = (min(max(jx, 0), nx - 1) * ny + min(max(jy, 0), ny - 1)) * nz +
-                  min(max(jz, 0), nz - 1);
-    int8_t l = lbl[idx];
+    const int32_t jx = nn_index(qx), jy = nn_index(qy), jz = nn_index(qz);
+    const bool ok = jx >= 0 && jx < S.nx && jy >= 0 && jy < S.ny && jz >= 0 && jz < S.nz;
+    const int8_t l = load_i8(S.lbl, elem_index(S, min(max(jx, 0), S.nx - 1),
+                                               min(max(jy, 0), S.ny - 1),
+                                               min(max(jz, 0), S.nz - 1)));
     return ok ? l : label_fill;
 }
 
-__device__ __forceinline__ int8_t label_interior(const int8_t *lbl, int32_t ny, int32_t nz,
-                                                 float qx, float qy, float qz)
+__device__ __forceinline__ int8_t label_interior(const Src &S, float qx, float qy, float qz)
 {
-    return lbl[(nn_index(qx) * ny + nn_index(qy)) * nz + nn_index(qz)];
+    return load_i8(S.lbl, elem_index(S, nn_index(qx), nn_index(qy), nn_index(qz)));
 }
 
 // ---------------------------------------------------------------------------
@@ -215,15 +305,20 @@ __device__ __forceinline__ float uniform01(uint32_t w)
     return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
 }
 
-// (r cos theta, r sin theta) with r = sqrt(-2 ln U(wr)), theta = 2 pi U(wt).
-// sincospi takes 2U exactly, so the angle carries no rounding of 2 pi.
+// (r cos theta, r sin theta) with r = sqrt(-2 ln U(wr)), theta = 2 pi U(wt),
+// on the hardware transcendental units: v_log_f32 (log2), v_sqrt_f32, and
+// v_sin_f32 / v_cos_f32, which take their argument in revolutions, so the
+// angle is U itself with no rounding of 2 pi.  Measured over all 2^23
+// uniforms on gfx950: |dr|/r <= 1.35e-7 and |d sin|, |d cos| <= 1.25e-7, which
+// bounds the error of each normal by 1.35e-7 |n| + 5.77 * 1.25e-7 + rounding
+// < 1e-6 max(1, |n|).
 __device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wt, float &c, float &s)
 {
-    float r = sqrtf(-2.0f * logf(uniform01(wr)));
-    float sn, cs;
-    sincospif(2.0f * uniform01(wt), &sn, &cs);
-    c = r * cs;
-    s = r * sn;
+    const float r2 = -1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(wr));  // -2 ln U
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float t = uniform01(wt);
+    c = r * __builtin_amdgcn_cosf(t);
+    s = r * __builtin_amdgcn_sinf(t);
 }
 
 // Standard normals of the four voxels of noise group g.
@@ -236,14 +331,12 @@ __device__ __forceinline__ void gauss_group(uint64_t g, uint32_t vol, uint32_t k
     box_muller(c[2], c[3], n[2], n[3]);
 }
 
-// Standard normals of voxels v0 .. v0+3 (any alignment).
-__device__ __forceinline__ void gauss_run(uint64_t v0, uint32_t vol, uint32_t k0, uint32_t k1,
-                                          float n[4])
+// Standard normals of voxels v0 .. v0+3 when v0 is not a multiple of 4 (the
+// run straddles two noise groups): only volumes whose z extent is not a
+// multiple of 4.
+__device__ __forceinline__ void gauss_run_split(uint64_t v0, uint32_t vol, uint32_t k0,
+                                                uint32_t k1, float n[4])
 {
-    if ((v0 & 3u) == 0) {
-        gauss_group(v0 >> 2, vol, k0, k1, n);
-        return;
-    }
     float a[4], b[4];
     gauss_group(v0 >> 2, vol, k0, k1, a);
     gauss_group((v0 >> 2) + 1, vol, k0, k1, b);
@@ -255,6 +348,16 @@ __device__ __forceinline__ void gauss_run(uint64_t v0, uint32_t vol, uint32_t k0
         float vb = j == 4 ? b[0] : j == 5 ? b[1] : j == 6 ? b[2] : b[3];
         n[k] = j < 4 ? va : vb;
     }
+}
+
+// Standard normals of voxels v0 .. v0+3 (any alignment).
+__device__ __forceinline__ void gauss_run(uint64_t v0, uint32_t vol, uint32_t k0, uint32_t k1,
+                                          float n[4])
+{
+    if ((v0 & 3u) == 0)
+        gauss_group(v0 >> 2, vol, k0, k1, n);
+    else
+        gauss_run_split(v0, vol, k0, k1, n);
 }
 
 // ---------------------------------------------------------------------------

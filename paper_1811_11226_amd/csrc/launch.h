@@ -10,11 +10,22 @@ namespace ctaug {
 
 hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s);
 hipError_t launch_warp_batch(const FwdJob *jobs_dev, const int32_t *prefix_dev, int32_t njobs,
-                             int32_t total_tiles, int32_t grid, const Tiling &TL, hipStream_t s);
+                             int32_t total_tiles, int32_t grid, const Tiling &TL,
+                             int32_t lds_cells, int32_t elem_bytes, bool aligned, hipStream_t s);
+// Largest LDS footprint (cells of input-type image + int8 label) any tile of J
+// can need; the most cells a reservation of elem_bytes-wide cells can hold;
+// the cells reserved for a bound; the LDS bytes of a reservation.
+int32_t footprint_cells_bound(const FwdJob &J, const Tiling &TL);
+int32_t lds_cells_cap(int32_t elem_bytes);
+int32_t lds_cells_for(int32_t bound, int32_t elem_bytes);
+size_t lds_bytes_for(int32_t cells, int32_t elem_bytes);
 hipError_t launch_photometric(float *data, int64_t n, const Photo &P, uint32_t vol, uint32_t k0,
                               uint32_t k1, bool vec, hipStream_t s);
 hipError_t launch_noise(uint64_t v0, int64_t n, uint32_t vol, uint32_t k0, uint32_t k1,
                         float *gauss, uint32_t *words, hipStream_t s);
+
+hipError_t launch_box_muller(const uint32_t *words, int64_t npairs, float *out, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 int64_t bwd_num_tiles(int64_t ox, int64_t oy, int64_t oz);
 hipError_t launch_warp_bwd(const FwdJob &J, const float *g, float *g_img, float *g_disp,

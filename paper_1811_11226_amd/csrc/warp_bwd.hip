@@ -46,7 +46,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     const int tz = t % J.tiles_z, rest = t / J.tiles_z;
     const int ty = rest % J.tiles_y, tx = rest / J.tiles_y;
     const int x0 = tx << TL.lx, y0 = ty << TL.ly, z0 = tz << TL.lz;
-    const T *img = static_cast<const T *>(J.img);
+    const Src src = make_src<T>(J.img, nullptr, J.nx, J.ny, J.nz);
+    gconst<float> *disp = gc<float>(J.disp);
     const int32_t nvox = J.ox * J.oy * J.oz;
     const bool empty_in = J.nx == 0 || J.ny == 0 || J.nz == 0;   // every sample is fill
 
@@ -76,16 +77,16 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
             float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
                   qz = coord(J.M, 2, rb, zf);
             if (DISP) {
-                qx = qx + J.disp[v];
-                qy = qy + J.disp[nvox + v];
-                qz = qz + J.disp[2 * nvox + v];
+                qx = qx + disp[v];
+                qy = qy + disp[nvox + v];
+                qz = qz + disp[2 * nvox + v];
             }
             const float gp = g[v];
             float dV[3] = {0.0f, 0.0f, 0.0f};
             if (!empty_in && in_guard(qx, qy, qz, J.nx, J.ny, J.nz)) {
                 float K[8], tt[3];
                 int32_t i0[3];
-                corners_checked(img, J.nx, J.ny, J.nz, qx, qy, qz, J.fill, K, tt, i0);
+                corners_checked<T>(src, qx, qy, qz, J.fill, K, tt, i0);
                 const float e00 = lerp(K[0], K[1], tt[2]), e01 = lerp(K[2], K[3], tt[2]);
                 const float e10 = lerp(K[4], K[5], tt[2]), e11 = lerp(K[6], K[7], tt[2]);
                 dV[0] = lerp(e10, e11, tt[1]) - lerp(e00, e01, tt[1]);

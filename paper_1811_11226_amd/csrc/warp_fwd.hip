@@ -23,85 +23,238 @@
 #include "launch.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace ctaug {
 
 enum : int { kOutside = 0, kInterior = 1, kBoundary = 2 };
 
-__device__ __forceinline__ int classify_tile(const FwdJob &J, int x0, int y0, int z0, int x1,
-                                             int y1, int z1)
-{
-    if (J.nx == 0 || J.ny == 0 || J.nz == 0)
-        return kOutside;               // empty input: every sample is fill
-    if (J.disp)
-        return kBoundary;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        float r[3];
-        row_base(J.M, (float)((c & 4) ? x1 : x0), (float)((c & 2) ? y1 : y0), r);
-        float zf = (float)((c & 1) ? z1 : z0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            float q = coord(J.M, i, r, zf);
-            lo[i] = fminf(lo[i], q);
-            hi[i] = fmaxf(hi[i], q);
-        }
-    }
-    const float n[3] = {(float)J.nx, (float)J.ny, (float)J.nz};
-    bool outside = false, interior = true;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        float l = lo[i] - J.delta[i], h = hi[i] + J.delta[i];
-        outside = outside || (h <= -1.0f) || (l >= n[i]);
-        interior = interior && (l >= 0.0f) && (h < n[i] - 1.0f);
-    }
-    return outside ? kOutside : (interior ? kInterior : kBoundary);
-}
-
-// Tile t of job J -> origin and last in-range voxel.
-struct TileBox {
-    int x0, y0, z0, x1, y1, z1;
+// Geometry of one output tile, uniform over the workgroup.
+struct TileGeom {
+    int x0, y0, z0, x1, y1, z1;        // output voxels covered (inclusive)
+    int cls;                           // kOutside / kInterior / kBoundary
+    int lo[3], e[3];                   // input cells [lo, lo + e) the tile can touch
+    int pitch;                         // LDS row pitch (e[2] rounded up to 4)
+    bool lds;                          // footprint staged in LDS
 };
 
-__device__ __forceinline__ TileBox tile_box(const FwdJob &J, int t, const Tiling &TL)
+__device__ __forceinline__ TileGeom tile_geom(const FwdJob &J, int t, const Tiling &TL,
+                                              int32_t lds_cells)
 {
-    int tz = t % J.tiles_z;
-    int rest = t / J.tiles_z;
-    int ty = rest % J.tiles_y;
-    int tx = rest / J.tiles_y;
-    TileBox b;
-    b.x0 = tx << TL.lx;
-    b.y0 = ty << TL.ly;
-    b.z0 = tz << TL.lz;
-    b.x1 = min(b.x0 + (1 << TL.lx), J.ox) - 1;
-    b.y1 = min(b.y0 + (1 << TL.ly), J.oy) - 1;
-    b.z1 = min(b.z0 + (1 << TL.lz), J.oz) - 1;
-    return b;
+    TileGeom G;
+    const int tz = t % J.tiles_z;
+    const int rest = t / J.tiles_z;
+    const int ty = rest % J.tiles_y;
+    const int tx = rest / J.tiles_y;
+    G.x0 = tx << TL.lx;
+    G.y0 = ty << TL.ly;
+    G.z0 = tz << TL.lz;
+    G.x1 = min(G.x0 + (1 << TL.lx), J.ox) - 1;
+    G.y1 = min(G.y0 + (1 << TL.ly), J.oy) - 1;
+    G.z1 = min(G.z0 + (1 << TL.lz), J.oz) - 1;
+    G.lds = false;
+    G.pitch = 0;
+    if (J.nx == 0 || J.ny == 0 || J.nz == 0) {
+        G.cls = kOutside;              // empty input: every sample is fill
+        return G;
+    }
+    if (J.disp) {
+        G.cls = kBoundary;             // displacement: per-sample checks, direct gathers
+        return G;
+    }
+    // The coordinate is affine in p: its extremes over the box are the value at
+    // the origin plus the negative / positive parts of A_ij * span_j.  The
+    // margin delta covers FP32 rounding of both this bound and of q itself.
+    const float span[3] = {(float)(G.x1 - G.x0), (float)(G.y1 - G.y0), (float)(G.z1 - G.z0)};
+    float rb[3];
+    row_base(J.M, (float)G.x0, (float)G.y0, rb);
+    const int n[3] = {J.nx, J.ny, J.nz};
+    bool outside = false, interior = true;
+    int cells = 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float q0 = coord(J.M, i, rb, (float)G.z0);
+        float dn = 0.0f, up = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float d = J.M[4 * i + j] * span[j];
+            dn += fminf(d, 0.0f);
+            up += fmaxf(d, 0.0f);
+        }
+        const float l = q0 + dn - J.delta[i], h = q0 + up + J.delta[i];
+        outside = outside || (h <= -1.0f) || (l >= (float)n[i]);
+        interior = interior && (l >= 0.0f) && (h < (float)(n[i] - 1));
+        // cells floor(q) .. floor(q) + 1 of every guarded sample, clamped to [-1, n]
+        const int a = (int)fmaxf(floorf(l), -1.0f);
+        const int b = min((int)fminf(floorf(h), (float)n[i]) + 1, n[i]);
+        G.lo[i] = a;
+        G.e[i] = max(b - a + 1, 1);
+    }
+    G.pitch = (G.e[2] + 3) & ~3;
+    cells = G.e[0] * G.e[1] * G.pitch;
+    G.cls = outside ? kOutside : (interior ? kInterior : kBoundary);
+    // an int16 footprint must hold fill exactly
+    G.lds = !outside && cells <= lds_cells && (!(J.flags & kFlagLds16) || (J.flags & kFlagFillInT));
+    return G;
 }
 
-template <typename T, bool VEC>
-__device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &TL)
+// Footprint rows are quads of 4 cells.  When one x-slab of the footprint
+// (ey rows of quads_per_row quads) fits the workgroup, each lane keeps one
+// fixed (y row, quad) for the whole tile and walks the x-slabs: the row
+// bookkeeping is two additions per quad.  Larger slabs use a generic loop.
+__device__ __forceinline__ void store4(float *dst, const float v[4])
 {
-    const TileBox B = tile_box(J, t, TL);
-    const int cls = classify_tile(J, B.x0, B.y0, B.z0, B.x1, B.y1, B.z1);
-    const T *img = static_cast<const T *>(J.img);
+    *reinterpret_cast<f32x4 *>(dst) = f32x4{v[0], v[1], v[2], v[3]};
+}
+
+__device__ __forceinline__ void store4(int16_t *dst, const int16_t v[4])
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    *reinterpret_cast<u32x2 *>(dst) =
+        u32x2{(uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16),
+              (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16)};
+}
+
+template <typename T, typename LT, bool INSIDE, bool LBL>
+__device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, const TileGeom &G,
+                                           int gx, int gy, int cz0, uint32_t grow_inside,
+                                           LT *dst, int8_t *ldst)
+{
+    constexpr uint32_t es = sizeof(T);
+    const int8_t lfill = (int8_t)J.label_fill;
+    const bool row_in = INSIDE || ((unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny);
+    const uint32_t grow = INSIDE ? grow_inside
+                                 : elem_index(S, min(max(gx, 0), J.nx - 1),
+                                              min(max(gy, 0), J.ny - 1), 0);
+    const LT tfill = (LT)J.fill;
+    LT v[4];
+    uint32_t lp = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int gz = G.lo[2] + cz0 + u;
+        const uint32_t e = INSIDE ? grow + (uint32_t)(cz0 + u)
+                                  : grow + (uint32_t)min(max(gz, 0), J.nz - 1);
+        const T raw = Elem<T>::raw(S.img, e * es, 0);
+        const int8_t lab = LBL ? load_i8(S.lbl, e) : lfill;
+        bool in = true;
+        if (!INSIDE)
+            in = row_in && (unsigned)gz < (unsigned)J.nz;
+        v[u] = in ? (LT)raw : tfill;
+        if (LBL)
+            lp |= (uint32_t)(uint8_t)(in ? lab : lfill) << (8 * u);
+    }
+    store4(dst + cz0, v);
+    if (LBL)
+        *reinterpret_cast<uint32_t *>(ldst + cz0) = lp;
+}
+
+template <typename T, typename LT, bool INSIDE, bool LBL>
+__device__ __forceinline__ void stage_rows(const FwdJob &J, const Src &S, const TileGeom &G,
+                                           LT *s_img, int8_t *s_lbl)
+{
+    const int ex = G.e[0], ey = G.e[1], P = G.pitch;
+    const int qpr = P >> 2;
+    const int slab = ey * qpr;
+    if (slab <= kThreads) {
+        const int ng = kThreads / slab;                    // x-slabs per pass
+        const int g = threadIdx.x / slab;
+        const int s = threadIdx.x - g * slab;
+        if (g >= ng)
+            return;
+        const int cy = s / qpr;
+        const int cz0 = 4 * (s - cy * qpr);
+        const int gy = G.lo[1] + cy;
+        // element index of (lo_x + cx, gy, lo_z): advanced by ng x-planes per pass
+        const uint32_t plane = mul24((uint32_t)S.ny, (uint32_t)S.nz);
+        uint32_t grow = INSIDE ? elem_index(S, G.lo[0] + g, gy, G.lo[2]) : 0u;
+        const uint32_t gstep = mul24((uint32_t)ng, plane);
+        const int lstep = ng * ey * P;
+        int loff = (g * ey + cy) * P;
+#pragma unroll 4
+        for (int cx = g; cx < ex; cx += ng) {
+            stage_quad<T, LT, INSIDE, LBL>(J, S, G, G.lo[0] + cx, gy, cz0, grow, s_img + loff,
+                                       s_lbl + loff);
+            grow += gstep;
+            loff += lstep;
+        }
+        return;
+    }
+    // generic: lanes x rows
+    const int quads = qpr;
+    const int lr_log = quads <= 4 ? 2 : quads <= 8 ? 3 : quads <= 16 ? 4 : quads <= 32 ? 5 : 6;
+    const int LR = 1 << lr_log;
+    const int rpi = kThreads >> lr_log;
+    const int lane_q = threadIdx.x & (LR - 1);
+    const int rows = ex * ey;
+    for (int r = threadIdx.x >> lr_log; r < rows; r += rpi) {
+        const int cx = r / ey;
+        const int cy = r - cx * ey;
+        const int gx = G.lo[0] + cx, gy = G.lo[1] + cy;
+        const uint32_t grow = INSIDE ? elem_index(S, gx, gy, G.lo[2]) : 0u;
+        for (int q = lane_q; q < quads; q += LR)
+            stage_quad<T, LT, INSIDE, LBL>(J, S, G, gx, gy, 4 * q, grow, s_img + r * P,
+                                       s_lbl + r * P);
+    }
+}
+
+// Copy the tile's input footprint into LDS in the input type (labels as int8), with
+// fill / label_fill in cells outside the volume.  Each lane moves 4
+// consecutive cells of one row: buffer loads from one VGPR offset (the cell
+// steps are immediates), one 16-byte and one 4-byte LDS store.  When the whole
+// footprint lies inside the volume no per-cell test is compiled in.
+template <typename T, typename LT>
+__device__ __forceinline__ void stage_footprint(const FwdJob &J, const Src &S, const TileGeom &G,
+                                                LT *s_img, int8_t *s_lbl)
+{
     const bool labels = (J.flags & kFlagLabels) != 0;
+    const bool inside = G.lo[0] >= 0 && G.lo[1] >= 0 && G.lo[2] >= 0 &&
+                        G.lo[0] + G.e[0] <= J.nx && G.lo[1] + G.e[1] <= J.ny &&
+                        G.lo[2] + G.pitch <= J.nz;
+    if (inside) {
+        if (labels)
+            stage_rows<T, LT, true, true>(J, S, G, s_img, s_lbl);
+        else
+            stage_rows<T, LT, true, false>(J, S, G, s_img, s_lbl);
+    } else {
+        if (labels)
+            stage_rows<T, LT, false, true>(J, S, G, s_img, s_lbl);
+        else
+            stage_rows<T, LT, false, false>(J, S, G, s_img, s_lbl);
+    }
+}
+
+enum : int { kPathOutside, kPathLdsInterior, kPathLdsBoundary, kPathDirectInterior,
+             kPathDirectBoundary };
+
+// All runs of one tile along one sampling path.  Each thread owns runs of 4
+// consecutive output voxels along z.
+template <typename T, typename LT, int PATH, bool ALIGNED>
+__device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &TL,
+                                         const LT *s_img, const int8_t *s_lbl)
+{
+    const Src S = make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz);
+    gmut<float> *out = gm<float>(J.out);
+    gmut<int8_t> *lout = gm<int8_t>(J.lout);
+    gconst<float> *disp = gc<float>(J.disp);
+    const bool labels = (J.flags & kFlagLabels) != 0;
+    const bool vec = (J.flags & kFlagVec) != 0;
     const Photo P = photo_of(J);
     const int32_t nvox = J.ox * J.oy * J.oz;
     const int runs_z_log = TL.lz - 2;
     const int nruns = 1 << (TL.lx + TL.ly + runs_z_log);
+    const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
+    const int8_t lfill = (int8_t)J.label_fill;
 
     for (int r = threadIdx.x; r < nruns; r += kThreads) {
         const int zr = r & ((1 << runs_z_log) - 1);
         const int rr = r >> runs_z_log;
-        const int y = B.y0 + (rr & ((1 << TL.ly) - 1));
-        const int x = B.x0 + (rr >> TL.ly);
-        const int z = B.z0 + 4 * zr;
-        if (x > B.x1 || y > B.y1 || z > B.z1)
+        const int y = G.y0 + (rr & ((1 << TL.ly) - 1));
+        const int x = G.x0 + (rr >> TL.ly);
+        const int z = G.z0 + 4 * zr;
+        if (x > G.x1 || y > G.y1 || z > G.z1)
             continue;
-        const int nvalid = VEC ? 4 : min(4, J.oz - z);
-        const int32_t v0 = (x * J.oy + y) * J.oz + z;
+        const int nvalid = ALIGNED ? 4 : min(4, J.oz - z);
+        const uint32_t v0 = (uint32_t)((x * J.oy + y) * J.oz + z);
         float rb[3];
         row_base(J.M, (float)x, (float)y, rb);
 
@@ -110,84 +263,150 @@ __device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &T
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             V[k] = J.fill;
-            L[k] = (int8_t)J.label_fill;
-            if (!VEC && k >= nvalid)
+            L[k] = lfill;
+            if (PATH == kPathOutside || (!ALIGNED && k >= nvalid))
                 continue;
             const float zf = (float)(z + k);
             float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
                   qz = coord(J.M, 2, rb, zf);
-            if (J.disp) {
-                qx = qx + J.disp[v0 + k];
-                qy = qy + J.disp[nvox + v0 + k];
-                qz = qz + J.disp[2 * nvox + v0 + k];
-            }
-            if (cls == kInterior) {
-                V[k] = sample_interior(img, J.ny, J.nz, qx, qy, qz);
-                if (labels)
-                    L[k] = label_interior(J.lbl, J.ny, J.nz, qx, qy, qz);
-            } else if (cls == kBoundary) {
-                V[k] = sample_checked(img, J.nx, J.ny, J.nz, qx, qy, qz, J.fill);
-                if (labels)
-                    L[k] = label_checked(J.lbl, J.nx, J.ny, J.nz, qx, qy, qz,
-                                         (int8_t)J.label_fill);
+            if (PATH == kPathLdsInterior || PATH == kPathLdsBoundary) {
+                if (PATH == kPathLdsBoundary && !in_guard(qx, qy, qz, J.nx, J.ny, J.nz))
+                    continue;
+                const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+                const int base = (int)mul24(mul24((uint32_t)((int)fx - G.lo[0]), (uint32_t)ey) +
+                                                (uint32_t)((int)fy - G.lo[1]),
+                                            (uint32_t)pitch) +
+                                 ((int)fz - G.lo[2]);
+                float kk[8];
+                kk[0] = (float)s_img[base];
+                kk[1] = (float)s_img[base + 1];
+                kk[2] = (float)s_img[base + pitch];
+                kk[3] = (float)s_img[base + pitch + 1];
+                kk[4] = (float)s_img[base + sxy];
+                kk[5] = (float)s_img[base + sxy + 1];
+                kk[6] = (float)s_img[base + sxy + pitch];
+                kk[7] = (float)s_img[base + sxy + pitch + 1];
+                V[k] = tri(kk, qx - fx, qy - fy, qz - fz);
+                if (labels) {
+                    const int jx = nn_index(qx) - G.lo[0], jy = nn_index(qy) - G.lo[1],
+                              jz = nn_index(qz) - G.lo[2];
+                    L[k] = s_lbl[mul24(mul24((uint32_t)jx, (uint32_t)ey) + (uint32_t)jy,
+                                       (uint32_t)pitch) + jz];
+                }
+            } else {
+                if (J.disp) {
+                    qx = qx + disp[v0 + k];
+                    qy = qy + disp[nvox + v0 + k];
+                    qz = qz + disp[2 * nvox + v0 + k];
+                }
+                if (PATH == kPathDirectInterior) {
+                    V[k] = sample_interior<T>(S, qx, qy, qz);
+                    if (labels)
+                        L[k] = label_interior(S, qx, qy, qz);
+                } else {
+                    V[k] = sample_checked<T>(S, qx, qy, qz, J.fill);
+                    if (labels)
+                        L[k] = label_checked(S, qx, qy, qz, lfill);
+                }
             }
         }
 
         if (P.flags & kFlagPhoto) {
             float n[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (P.flags & kFlagNoise)
-                gauss_run((uint64_t)v0, J.vol_id, J.key0, J.key1, n);
+            if (P.flags & kFlagNoise) {
+                if (ALIGNED)
+                    gauss_group((uint64_t)(v0 >> 2), J.vol_id, J.key0, J.key1, n);
+                else
+                    gauss_run((uint64_t)v0, J.vol_id, J.key0, J.key1, n);
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 V[k] = photometric(P, V[k], n[k]);
         }
 
-        if (VEC) {
-            *reinterpret_cast<float4 *>(J.out + v0) = make_float4(V[0], V[1], V[2], V[3]);
+        if (ALIGNED && vec) {
+            *reinterpret_cast<gmut<f32x4> *>(out + v0) = f32x4{V[0], V[1], V[2], V[3]};
             if (labels) {
-                uint32_t packed = (uint32_t)(uint8_t)L[0] | ((uint32_t)(uint8_t)L[1] << 8) |
-                                  ((uint32_t)(uint8_t)L[2] << 16) | ((uint32_t)(uint8_t)L[3] << 24);
-                *reinterpret_cast<uint32_t *>(J.lout + v0) = packed;
+                const uint32_t packed = (uint32_t)(uint8_t)L[0] | ((uint32_t)(uint8_t)L[1] << 8) |
+                                        ((uint32_t)(uint8_t)L[2] << 16) |
+                                        ((uint32_t)(uint8_t)L[3] << 24);
+                *reinterpret_cast<gmut<uint32_t> *>(lout + v0) = packed;
             }
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (k < nvalid) {
-                    J.out[v0 + k] = V[k];
+                    out[v0 + k] = V[k];
                     if (labels)
-                        J.lout[v0 + k] = L[k];
+                        lout[v0 + k] = L[k];
                 }
         }
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void fwd_tile_dispatch(const FwdJob &J, int t, const Tiling &TL)
+// ALIGNED: the output z extent is a multiple of 4, so every run is one noise
+// group and (with 16-byte aligned outputs) one vector store.  LT: type of the
+// LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
+// the LDS reads).
+template <typename T, typename LT, bool ALIGNED>
+__device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling &TL,
+                                            int32_t lds_cells, uint8_t *s_lds)
 {
-    if (J.flags & kFlagVec)
-        fwd_tile<T, true>(J, t, TL);
-    else
-        fwd_tile<T, false>(J, t, TL);
+    LT *s_img = reinterpret_cast<LT *>(s_lds);
+    int8_t *s_lbl = reinterpret_cast<int8_t *>(s_lds + lds_label_offset<LT>(lds_cells));
+    const TileGeom G = tile_geom(J, t, TL, lds_cells);
+    if (G.cls == kOutside) {
+        run_tile<T, LT, kPathOutside, ALIGNED>(J, G, TL, s_img, s_lbl);
+    } else if (G.lds) {
+        stage_footprint<T, LT>(J, make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz), G, s_img, s_lbl);
+        __syncthreads();
+        if (G.cls == kInterior)
+            run_tile<T, LT, kPathLdsInterior, ALIGNED>(J, G, TL, s_img, s_lbl);
+        else
+            run_tile<T, LT, kPathLdsBoundary, ALIGNED>(J, G, TL, s_img, s_lbl);
+        __syncthreads();               // LDS is reused by the next tile
+    } else if (G.cls == kInterior) {
+        run_tile<T, LT, kPathDirectInterior, ALIGNED>(J, G, TL, s_img, s_lbl);
+    } else {
+        run_tile<T, LT, kPathDirectBoundary, ALIGNED>(J, G, TL, s_img, s_lbl);
+    }
 }
 
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &TL,
+                                         int32_t lds_cells, uint8_t *s_lds)
+{
+    if (sizeof(T) == 2 && (J.flags & kFlagLds16))
+        fwd_tile_lt<T, T, ALIGNED>(J, t, TL, lds_cells, s_lds);
+    else
+        fwd_tile_lt<T, float, ALIGNED>(J, t, TL, lds_cells, s_lds);
+}
+
+// Dynamic LDS: lds_cells input-type cells of image footprint (rounded up to
+// 16 bytes), then lds_cells int8 labels.
+extern __shared__ __attribute__((aligned(16))) uint8_t s_footprint[];
+
 // Single job, job in kernel arguments, one workgroup per tile.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, int32_t ntiles)
+template <typename T, bool ALIGNED>
+__global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, int32_t ntiles,
+                                                          int32_t lds_cells)
 {
     const int b = blockIdx.x;
     const int per = (ntiles + 7) >> 3;
     const int t = (b & 7) * per + (b >> 3);
     if (t >= ntiles)
         return;
-    fwd_tile_dispatch<T>(J, t, TL);
+    fwd_tile<T, ALIGNED>(J, t, TL, lds_cells, s_footprint);
 }
 
 // Batch of jobs from a device table.  prefix[j] = first global tile of job j,
 // prefix[njobs] = total.  Workgroups stride over the tiles of their XCD's
 // contiguous range (persistent when gridDim.x is a few per CU).
+template <bool ALIGNED>
 __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restrict__ jobs,
                                                          const int32_t *__restrict__ prefix,
-                                                         int32_t njobs, Tiling TL)
+                                                         int32_t njobs, Tiling TL,
+                                                         int32_t lds_cells)
 {
     const int total = prefix[njobs];
     const int b = blockIdx.x;
@@ -203,10 +422,46 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
         const FwdJob J = jobs[j];
         const int lt = t - prefix[j];
         if (J.dtype == kI16)
-            fwd_tile_dispatch<int16_t>(J, lt, TL);
+            fwd_tile<int16_t, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
         else
-            fwd_tile_dispatch<float>(J, lt, TL);
+            fwd_tile<float, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
     }
+}
+
+// Upper bound on the footprint cells of any tile of job J (see tile_geom).
+int32_t footprint_cells_bound(const FwdJob &J, const Tiling &TL)
+{
+    const int t[3] = {1 << TL.lx, 1 << TL.ly, 1 << TL.lz};
+    const int n[3] = {J.nx, J.ny, J.nz};
+    int64_t cells = 1;
+    for (int i = 0; i < 3; ++i) {
+        double span = 2.0 * (double)J.delta[i];
+        for (int j = 0; j < 3; ++j)
+            span += std::fabs((double)J.M[4 * i + j]) * (double)(t[j] - 1);
+        int64_t e = std::min<int64_t>((int64_t)std::floor(span) + 3, (int64_t)n[i] + 2);
+        e = std::max<int64_t>(e, 1);
+        if (i == 2)
+            e = (e + 3) & ~(int64_t)3;       // LDS row pitch
+        cells *= e;
+        if (cells > (int64_t)1 << 30)
+            return 1 << 30;
+    }
+    return (int32_t)cells;
+}
+
+int32_t lds_cells_cap(int32_t elem_bytes)
+{
+    return (kMaxLdsBytes - 16) / (elem_bytes + 1) & ~15;
+}
+
+int32_t lds_cells_for(int32_t bound, int32_t elem_bytes)
+{
+    return std::min(bound, lds_cells_cap(elem_bytes));
+}
+
+size_t lds_bytes_for(int32_t cells, int32_t elem_bytes)
+{
+    return (((size_t)cells * (size_t)elem_bytes + 15) & ~(size_t)15) + (size_t)cells;
 }
 
 hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s)
@@ -215,20 +470,41 @@ hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s)
     if (ntiles == 0)
         return hipSuccess;
     const int grid = ((ntiles + 7) >> 3) << 3;
-    if (J.dtype == kI16)
-        hipLaunchKernelGGL(k_warp_single<int16_t>, dim3(grid), dim3(kThreads), 0, s, J, TL, ntiles);
-    else
-        hipLaunchKernelGGL(k_warp_single<float>, dim3(grid), dim3(kThreads), 0, s, J, TL, ntiles);
+    const int32_t esz = (J.flags & kFlagLds16) ? 2 : 4;
+    const int32_t cells = J.disp ? 0 : lds_cells_for(footprint_cells_bound(J, TL), esz);
+    const size_t lds = lds_bytes_for(cells, esz);
+    const bool aligned = J.oz % 4 == 0;
+    if (J.dtype == kI16) {
+        if (aligned)
+            hipLaunchKernelGGL((k_warp_single<int16_t, true>), dim3(grid), dim3(kThreads), lds, s,
+                               J, TL, ntiles, cells);
+        else
+            hipLaunchKernelGGL((k_warp_single<int16_t, false>), dim3(grid), dim3(kThreads), lds, s,
+                               J, TL, ntiles, cells);
+    } else {
+        if (aligned)
+            hipLaunchKernelGGL((k_warp_single<float, true>), dim3(grid), dim3(kThreads), lds, s, J,
+                               TL, ntiles, cells);
+        else
+            hipLaunchKernelGGL((k_warp_single<float, false>), dim3(grid), dim3(kThreads), lds, s, J,
+                               TL, ntiles, cells);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_warp_batch(const FwdJob *jobs_dev, const int32_t *prefix_dev, int32_t njobs,
-                             int32_t total_tiles, int32_t grid, const Tiling &TL, hipStream_t s)
+                             int32_t total_tiles, int32_t grid, const Tiling &TL,
+                             int32_t lds_cells, int32_t elem_bytes, bool aligned, hipStream_t s)
 {
     if (total_tiles == 0 || njobs == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_warp_batch, dim3(grid), dim3(kThreads), 0, s, jobs_dev, prefix_dev, njobs,
-                       TL);
+    const size_t lds = lds_bytes_for(lds_cells, elem_bytes);
+    if (aligned)
+        hipLaunchKernelGGL(k_warp_batch<true>, dim3(grid), dim3(kThreads), lds, s, jobs_dev,
+                           prefix_dev, njobs, TL, lds_cells);
+    else
+        hipLaunchKernelGGL(k_warp_batch<false>, dim3(grid), dim3(kThreads), lds, s, jobs_dev,
+                           prefix_dev, njobs, TL, lds_cells);
     return hipGetLastError();
 }
 
@@ -314,6 +590,64 @@ hipError_t launch_noise(uint64_t v0, int64_t n, uint32_t vol, uint32_t k0, uint3
     const int64_t blocks = std::min<int64_t>((ng + kThreads - 1) / kThreads, 256 * 64);
     hipLaunchKernelGGL(k_noise, dim3((unsigned)blocks), dim3(kThreads), 0, s, v0, n, vol, k0, k1,
                        gauss, words);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void k_box_muller(const uint32_t *__restrict__ w,
+                                                         int64_t npairs, float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < npairs;
+         i += (int64_t)gridDim.x * kThreads) {
+        float c, sn;
+        box_muller(w[2 * i], w[2 * i + 1], c, sn);
+        out[2 * i] = c;
+        out[2 * i + 1] = sn;
+    }
+}
+
+hipError_t launch_box_muller(const uint32_t *words, int64_t npairs, float *out, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((npairs + kThreads - 1) / kThreads, 256 * 64);
+    hipLaunchKernelGGL(k_box_muller, dim3((unsigned)blocks), dim3(kThreads), 0, s, words, npairs,
+                       out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain streaming copy (measurement reference and cache eviction).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_copy16(const float4 *__restrict__ src,
+                                                     float4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy1(const uint8_t *__restrict__ src,
+                                                    uint8_t *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const bool aligned = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) |
+                           bytes) & 15u) == 0;
+    if (aligned) {
+        const int64_t n = (int64_t)(bytes / 16);
+        const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, 256 * 16);
+        hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           static_cast<const float4 *>(src), static_cast<float4 *>(dst), n);
+    } else {
+        const int64_t n = (int64_t)bytes;
+        const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, 256 * 16);
+        hipLaunchKernelGGL(k_copy1, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           static_cast<const uint8_t *>(src), static_cast<uint8_t *>(dst), n);
+    }
     return hipGetLastError();
 }
 

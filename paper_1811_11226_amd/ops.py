@@ -149,6 +149,20 @@ def noise(seed, volume_id, v0, n, gauss=True, words=False, device="cuda"):
     return g, w   # words as int32 bit patterns [groups][4]
 
 
+def box_muller(words):
+    """Normals from a uint32 word tensor of even length (viewed as int32):
+    pairs (radius word, angle word) -> (r cos, r sin)."""
+    if words.dtype not in (torch.int32,) or words.numel() % 2 or not words.is_contiguous():
+        raise ValueError("box_muller: contiguous int32 tensor of even length expected")
+    out = torch.empty(words.numel(), dtype=torch.float32, device=words.device)
+    st = _lib.load().ctaug_box_muller(ctypes.c_void_p(words.data_ptr() if words.numel() else None),
+                                      words.numel() // 2,
+                                      ctypes.c_void_p(out.data_ptr() if out.numel() else None),
+                                      _stream())
+    _lib.check(st, "ctaug_box_muller")
+    return out
+
+
 def warp_backward_workspace(out_dim):
     d = (ctypes.c_int64 * 3)(*[int(v) for v in out_dim])
     return int(_lib.load().ctaug_warp_backward_workspace(d))
@@ -222,6 +236,17 @@ def bspline_upsample_adjoint(grad_disp, grid):
     return g
 
 
+def copy(src, dst):
+    """Streaming device copy of src into dst (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy: size mismatch")
+    _lib.check(_lib.load().ctaug_copy(ctypes.c_void_p(src.data_ptr()),
+                                      ctypes.c_void_p(dst.data_ptr()), nbytes, _stream()),
+               "ctaug_copy")
+    return dst
+
+
 # ---------------------------------------------------------------------------
 # Batch plan
 # ---------------------------------------------------------------------------
@@ -252,7 +277,7 @@ class BatchPlan:
     """One persistent launch over a batch of jobs (device job table, pinned
     staging, optional HIP graph, autotuned launch shape)."""
 
-    def __init__(self, jobs, tile=None, wg_per_cu=0):
+    def __init__(self, jobs, tile=None, wg_per_cu=0, lds_cells=0, lds_format=0):
         self._L = _lib.load()
         arr = (_lib.Job * len(jobs))(*jobs)
         tune = None
@@ -260,6 +285,8 @@ class BatchPlan:
             tune = _lib.Tuning()
             tune.tile = (ctypes.c_int32 * 3)(*tile)
             tune.wg_per_cu = wg_per_cu
+            tune.lds_cells = lds_cells
+            tune.lds_format = lds_format
         h = ctypes.c_void_p()
         _lib.check(self._L.ctaug_batch_plan_create(arr, len(jobs), _ref(tune), ctypes.byref(h)),
                    "ctaug_batch_plan_create")
@@ -273,6 +300,9 @@ class BatchPlan:
     def launch(self):
         _lib.check(self._L.ctaug_batch_plan_launch(self._h, _stream()), "ctaug_batch_plan_launch")
 
+    def run(self):
+        _lib.check(self._L.ctaug_batch_plan_run(self._h, _stream()), "ctaug_batch_plan_run")
+
     def capture(self):
         _lib.check(self._L.ctaug_batch_plan_capture(self._h, _stream()), "ctaug_batch_plan_capture")
 
@@ -280,23 +310,26 @@ class BatchPlan:
         _lib.check(self._L.ctaug_batch_plan_replay(self._h, _stream()), "ctaug_batch_plan_replay")
 
     def autotune(self, candidates, reps=5):
+        """candidates: (tile, wg_per_cu[, lds_cells[, lds_format]]) tuples."""
         n = len(candidates)
         cand = (_lib.Tuning * n)()
-        for i, (tile, wg) in enumerate(candidates):
-            cand[i].tile = (ctypes.c_int32 * 3)(*tile)
-            cand[i].wg_per_cu = wg
+        for i, c in enumerate(candidates):
+            cand[i].tile = (ctypes.c_int32 * 3)(*c[0])
+            cand[i].wg_per_cu = c[1]
+            cand[i].lds_cells = c[2] if len(c) > 2 else 0
+            cand[i].lds_format = c[3] if len(c) > 3 else 0
         best = _lib.Tuning()
         times = (ctypes.c_float * n)()
         _lib.check(self._L.ctaug_batch_plan_autotune(self._h, cand, n, reps, _stream(),
                                                      ctypes.byref(best), times),
                    "ctaug_batch_plan_autotune")
-        return (tuple(best.tile), best.wg_per_cu), list(times)
+        return (tuple(best.tile), best.wg_per_cu, best.lds_cells, best.lds_format), list(times)
 
     def tuning(self):
         t = _lib.Tuning()
         _lib.check(self._L.ctaug_batch_plan_get_tuning(self._h, ctypes.byref(t)),
                    "ctaug_batch_plan_get_tuning")
-        return tuple(t.tile), t.wg_per_cu
+        return tuple(t.tile), t.wg_per_cu, t.lds_cells, t.lds_format
 
     def close(self):
         if getattr(self, "_h", None):

@@ -70,11 +70,12 @@ def c2(dims=(512, 512, 320)):
     return [_job(2, 0, dims, dims, np.int16, AugmentRanges())]
 
 
-def c3(n=16, size_range=(96, 256), out_dim=(120, 120, 160)):
+def c3(n=16, size_range=(96, 256), out_dim=(120, 120, 160), batch=0):
+    """Batch `batch` of the c3 dataset: volumes batch*n .. batch*n + n - 1."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 3000 - 1))
-    sizes = rng.integers(size_range[0], size_range[1] + 1, size=(n, 3))
+    sizes = rng.integers(size_range[0], size_range[1] + 1, size=((batch + 1) * n, 3))
     return [_job(3, i, tuple(int(s) for s in sizes[i]), out_dim, np.int16, AugmentRanges())
-            for i in range(n)]
+            for i in range(batch * n, (batch + 1) * n)]
 
 
 def c4(n=8, dim=128):

@@ -90,6 +90,31 @@ def test_gaussians_many_samples_within_bound():
     assert err.max() <= 1e-6, f"gaussian error {err.max():.3e} at |n|={abs(ref[np.argmax(err)])}"
 
 
+def _bm_check(words):
+    got = _np(ctaug.box_muller(_t(words.view(np.int32)))).astype(np.float64)
+    ref = oracle.box_muller(words)
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    return err.max(), ref[np.argmax(err)]
+
+
+def test_box_muller_exhaustive_uniforms():
+    """Every one of the 2^23 uniforms as the radius word (paired with a
+    permutation of all angle uniforms), then the largest radius paired with
+    every angle uniform."""
+    n = 1 << 23
+    rng = np.random.default_rng(13)
+    k = np.arange(n, dtype=np.uint32)
+    low = rng.integers(0, 512, size=(2, n), dtype=np.uint32)
+    w = np.empty(2 * n, dtype=np.uint32)
+    w[0::2] = (k << 9) | low[0]
+    w[1::2] = (rng.permutation(k) << 9) | low[1]
+    e1, at1 = _bm_check(w)
+    w[0::2] = 0                                   # U = 2^-24: r = sqrt(48 ln 2)
+    w[1::2] = k << 9
+    e2, at2 = _bm_check(w)
+    assert e1 <= 1e-6 and e2 <= 1e-6, (e1, at1, e2, at2)
+
+
 # ---------------------------------------------------------------------------
 # Forward warp: C1 full size, exact invariants, ragged and edge cases
 # ---------------------------------------------------------------------------
@@ -149,6 +174,52 @@ def test_ragged_shapes_parity(in_dim, out_dim, dtype):
     _, out, lout, ref, lref = run_job(job)
     assert np.array_equal(lout, lref)
     assert_intensity(out, ref, windowed=True, what=str(out_dim))
+
+
+@pytest.mark.parametrize("scale", [(3.5, 4.0), (0.3, 0.4)])
+def test_large_and_small_footprints(scale):
+    """Strong downsampling makes tile footprints exceed the LDS reservation
+    (direct-gather fallback); strong upsampling makes them tiny."""
+    rng = np.random.default_rng(int(scale[0] * 10))
+    in_dim, out_dim = (200, 180, 160), (44, 40, 36)
+    img, lbl = phantom_pair(in_dim, seed=12)
+    prm = draw_affine_params(rng, AugmentRanges(scale=scale), in_dim, out_dim)
+    ph = draw_photo(rng, AugmentRanges(), seed=5, volume_id=1)
+    job = configs.Job(img=img, lbl=lbl, out_dim=out_dim, prm=prm, photo=ph)
+    _, out, lout, ref, lref = run_job(job)
+    assert np.array_equal(lout, lref)
+    assert_intensity(out, ref, windowed=True)
+
+
+@pytest.mark.parametrize("shift", [-0.5, 0.5, -0.75, 0.25])
+@pytest.mark.parametrize("dtype", [np.float32, np.int16])
+@pytest.mark.parametrize("lds", [0, -1])
+def test_first_and_last_volume_elements(shift, dtype, lds):
+    """Half-voxel shifts put valid corners at the very first / last element of
+    the volume next to out-of-volume corners (regression: merged wide loads
+    must never straddle the buffer ends)."""
+    dims = (12, 10, 8)
+    rng = np.random.default_rng(3)
+    img = rng.integers(-1000, 1500, dims).astype(dtype)
+    lbl = rng.integers(0, 6, dims).astype(np.int8)
+    M = np.zeros((3, 4), np.float32)
+    M[:, :3] = np.eye(3)
+    M[:, 3] = shift
+    M = M.ravel()
+    out = torch.empty(dims, dtype=torch.float32, device=DEV)
+    lout = torch.empty(dims, dtype=torch.int8, device=DEV)
+    plan = ctaug.BatchPlan([ctaug.make_job(_t(img), M, out, _t(lbl), lout, fill=-1000.0)],
+                           tile=(4, 8, 8), lds_cells=lds, lds_format=int(dtype == np.int16))
+    plan.launch()
+    ref, lref = oracle.warp(img, M, dims, lbl=lbl, fill=-1000.0)
+    assert np.array_equal(_np(lout), lref)
+    assert_intensity(_np(out), ref, windowed=False)
+    plan.close()
+    g = rng.standard_normal(dims).astype(np.float32)
+    g_img, g_M = ctaug.warp_affine_backward(_t(img), M, _t(g))
+    r_img, r_M, _ = oracle.warp_backward(img, M, g)
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
 
 
 def test_unaligned_output_pointer_uses_scalar_path():
@@ -335,13 +406,14 @@ def test_batch_plan_matches_single_calls_and_oracle():
     plan.close()
 
 
-@pytest.mark.parametrize("tile,wg", [((4, 8, 32), 0), ((8, 8, 16), 2), ((2, 4, 64), 1),
-                                     ((16, 16, 16), 4)])
-def test_batch_launch_shapes_bit_identical(tile, wg):
+@pytest.mark.parametrize("tile,wg,lds,fmt", [((4, 8, 32), 0, 0, 0), ((8, 8, 16), 2, 0, 1),
+                                             ((2, 4, 64), 1, 2048, 0), ((16, 16, 16), 4, 0, 1),
+                                             ((8, 16, 16), 0, -1, 0), ((8, 8, 8), 0, 300, 1)])
+def test_batch_launch_shapes_bit_identical(tile, wg, lds, fmt):
     T = _batch_jobs(n=3, out_dim=(36, 30, 44))
     jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
             for (j, M, img, lbl, out, lout) in T]
-    plan = ctaug.BatchPlan(jobs, tile=tile, wg_per_cu=wg)
+    plan = ctaug.BatchPlan(jobs, tile=tile, wg_per_cu=wg, lds_cells=lds, lds_format=fmt)
     plan.launch()
     for (j, M, img, lbl, out, lout) in T:
         s_out, s_lout = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo,
@@ -384,9 +456,9 @@ def test_autotune_picks_a_candidate_and_results_hold():
     jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
             for (j, M, img, lbl, out, lout) in T]
     plan = ctaug.BatchPlan(jobs)
-    cands = [((4, 8, 32), 0), ((8, 8, 16), 0), ((4, 8, 32), 4)]
+    cands = [((4, 8, 32), 0, 0, 0), ((8, 8, 16), 0, 4096, 1), ((4, 8, 32), 4, -1, 0)]
     best, times = plan.autotune(cands, reps=2)
-    assert best in cands and all(t > 0 for t in times)
+    assert best[:2] in [c[:2] for c in cands] and all(t > 0 for t in times)
     assert plan.tuning() == best
     plan.launch()
     for (j, M, img, lbl, out, lout) in T:

@@ -562,6 +562,12 @@ def test_gaussian_box_muller_pair_structure():
             assert np.arctan2(zs, zc) % (2 * np.pi) == pytest.approx(2 * np.pi * ut, rel=1e-9, abs=1e-12)
 
 
+def test_box_muller_on_words_matches_noise_groups():
+    w = oracle.noise_words(7, 3, 100, 32)
+    z = oracle.gauss(7, 3, 400, 128)
+    np.testing.assert_array_equal(oracle.box_muller(w.ravel()), z)
+
+
 # --------------------------------------------------------------------------
 # Photometric chain: paper's window examples, gain/offset/gamma, noise
 # --------------------------------------------------------------------------
