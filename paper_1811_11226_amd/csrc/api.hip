@@ -124,6 +124,18 @@ void set_tiles(FwdJob &J, const Tiling &TL)
     J.tiles_x = (J.ox + (1 << TL.lx) - 1) >> TL.lx;
     J.tiles_y = (J.oy + (1 << TL.ly) - 1) >> TL.ly;
     J.tiles_z = (J.oz + (1 << TL.lz) - 1) >> TL.lz;
+    J.sub[0] = TL.lx;
+    J.sub[1] = TL.ly;
+    J.sub[2] = TL.lz;
+}
+
+// Stage each tile of J in sub-tiles whose footprint fits `cells` LDS cells.
+void set_subtiles(FwdJob &J, const Tiling &TL, int32_t cells)
+{
+    const Tiling SL = choose_subtile(J, TL, cells);
+    J.sub[0] = SL.lx;
+    J.sub[1] = SL.ly;
+    J.sub[2] = SL.lz;
 }
 
 // Validate the arguments of one forward warp and build its descriptor.
@@ -578,6 +590,8 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     } else if (cells > lds_cells_cap(p->elem_bytes)) {
         return CTAUG_EINVAL;
     }
+    for (int i = 0; i < p->n; ++i)
+        set_subtiles(p->jobs[i], TL, cells);
     if (hipMemcpy(p->prefix_dev, prefix.data(), sizeof(int32_t) * (p->n + 1),
                   hipMemcpyHostToDevice) != hipSuccess)
         return CTAUG_EHIP;
@@ -697,9 +711,11 @@ extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug
     }
     if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
         return CTAUG_EHIP;
-    for (int i = 0; i < p->n; ++i)
+    for (int i = 0; i < p->n; ++i) {
         if (p->elem_bytes == 2)
             next[i].flags |= kFlagLds16;
+        set_subtiles(next[i], p->TL, p->lds_cells);
+    }
     p->jobs = next;
     std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
     return CTAUG_OK;

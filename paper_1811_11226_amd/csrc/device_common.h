@@ -49,6 +49,7 @@ struct FwdJob {
     float gain, offset, sigma, win_lo, inv_range, gamma;
     uint32_t vol_id, key0, key1;
     int32_t tiles_x, tiles_y, tiles_z; // tile grid of this job's output
+    int32_t sub[3];                    // log2 extents of the sub-tiles a tile is staged in
 };
 
 // Launch shape: tile extents as log2 (voxels), z extent >= 4.
@@ -283,20 +284,32 @@ __device__ __forceinline__ int8_t label_interior(const Src &S, float qx, float q
 // with key (k0, k1); uniforms ((w >> 9) + 0.5) 2^-23; Box-Muller pairs
 // (w0, w1) and (w2, w3).
 // ---------------------------------------------------------------------------
+// a ^ b ^ c in one VALU instruction (the compiler emits two when one operand
+// is uniform).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
         uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        uint32_t n0 = xor3((uint32_t)(p1 >> 32), c[1], k0);
+        uint32_t n2 = xor3((uint32_t)(p0 >> 32), c[3], k1);
         c[1] = (uint32_t)p1;
         c[3] = (uint32_t)p0;
         c[0] = n0;
         c[2] = n2;
+        // bump the key in SALU each round rather than keeping all ten round
+        // keys live in scalar registers across the caller's loops
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+        asm volatile("" : "+s"(k0), "+s"(k1));
     }
 }
 

@@ -29,30 +29,38 @@ namespace ctaug {
 
 enum : int { kOutside = 0, kInterior = 1, kBoundary = 2 };
 
+// LDS row pitch for rows of e cells: whole quads of 4 cells, and an odd
+// number of quads so that neighbouring rows start in different LDS banks
+// (rows a multiple of 8 cells apart would all fall on the same banks).
+__device__ __host__ __forceinline__ int lds_pitch(int e)
+{
+    const int p = (e + 3) & ~3;
+    return (p & 4) ? p : p + 4;
+}
+
 // Geometry of one output tile, uniform over the workgroup.
 struct TileGeom {
     int x0, y0, z0, x1, y1, z1;        // output voxels covered (inclusive)
     int cls;                           // kOutside / kInterior / kBoundary
     int lo[3], e[3];                   // input cells [lo, lo + e) the tile can touch
-    int pitch;                         // LDS row pitch (e[2] rounded up to 4)
+    int quads;                         // 4-cell quads staged per row: ceil(e[2] / 4)
+    int pitch;                         // LDS row pitch: 4 * quads, padded to 4 mod 8 cells
     bool lds;                          // footprint staged in LDS
 };
 
-__device__ __forceinline__ TileGeom tile_geom(const FwdJob &J, int t, const Tiling &TL,
-                                              int32_t lds_cells)
+// Geometry of the output box [x0, x1] x [y0, y1] x [z0, z1] (inclusive).
+__device__ __forceinline__ TileGeom box_geom(const FwdJob &J, int x0, int y0, int z0, int x1,
+                                             int y1, int z1, int32_t lds_cells)
 {
     TileGeom G;
-    const int tz = t % J.tiles_z;
-    const int rest = t / J.tiles_z;
-    const int ty = rest % J.tiles_y;
-    const int tx = rest / J.tiles_y;
-    G.x0 = tx << TL.lx;
-    G.y0 = ty << TL.ly;
-    G.z0 = tz << TL.lz;
-    G.x1 = min(G.x0 + (1 << TL.lx), J.ox) - 1;
-    G.y1 = min(G.y0 + (1 << TL.ly), J.oy) - 1;
-    G.z1 = min(G.z0 + (1 << TL.lz), J.oz) - 1;
+    G.x0 = x0;
+    G.y0 = y0;
+    G.z0 = z0;
+    G.x1 = x1;
+    G.y1 = y1;
+    G.z1 = z1;
     G.lds = false;
+    G.quads = 0;
     G.pitch = 0;
     if (J.nx == 0 || J.ny == 0 || J.nz == 0) {
         G.cls = kOutside;              // empty input: every sample is fill
@@ -90,7 +98,8 @@ __device__ __forceinline__ TileGeom tile_geom(const FwdJob &J, int t, const Tili
         G.lo[i] = a;
         G.e[i] = max(b - a + 1, 1);
     }
-    G.pitch = (G.e[2] + 3) & ~3;
+    G.quads = (G.e[2] + 3) >> 2;
+    G.pitch = lds_pitch(G.e[2]);
     cells = G.e[0] * G.e[1] * G.pitch;
     G.cls = outside ? kOutside : (interior ? kInterior : kBoundary);
     // an int16 footprint must hold fill exactly
@@ -115,30 +124,59 @@ __device__ __forceinline__ void store4(int16_t *dst, const int16_t v[4])
               (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16)};
 }
 
+// Four consecutive input cells at byte offset `off` copied into LDS cells of
+// type LT with one buffer load (16 bytes of FP32 or 8 bytes of int16; the
+// offset need only be element-aligned).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void copy_quad(rsrc_t r, uint32_t off, float *dst, float)
+{
+    *reinterpret_cast<u32x4 *>(dst) = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+}
+
+__device__ __forceinline__ void copy_quad(rsrc_t r, uint32_t off, int16_t *dst, int16_t)
+{
+    *reinterpret_cast<u32x2 *>(dst) = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+}
+
+__device__ __forceinline__ void copy_quad(rsrc_t r, uint32_t off, float *dst, int16_t)
+{
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    *reinterpret_cast<f32x4 *>(dst) =
+        f32x4{(float)(int16_t)(w.x & 0xffffu), (float)((int32_t)w.x >> 16),
+              (float)(int16_t)(w.y & 0xffffu), (float)((int32_t)w.y >> 16)};
+}
+
 template <typename T, typename LT, bool INSIDE, bool LBL>
 __device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, const TileGeom &G,
                                            int gx, int gy, int cz0, uint32_t grow_inside,
                                            LT *dst, int8_t *ldst)
 {
     constexpr uint32_t es = sizeof(T);
+    if (INSIDE) {
+        // every cell of the quad lies in the volume: one load per array
+        const uint32_t e = grow_inside + (uint32_t)cz0;
+        copy_quad(S.img, e * es, dst + cz0, T());
+        if (LBL)
+            *reinterpret_cast<uint32_t *>(ldst + cz0) =
+                __builtin_amdgcn_raw_buffer_load_b32(S.lbl, e, 0, 0);
+        return;
+    }
     const int8_t lfill = (int8_t)J.label_fill;
-    const bool row_in = INSIDE || ((unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny);
-    const uint32_t grow = INSIDE ? grow_inside
-                                 : elem_index(S, min(max(gx, 0), J.nx - 1),
-                                              min(max(gy, 0), J.ny - 1), 0);
+    const bool row_in = (unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny;
+    const uint32_t grow = elem_index(S, min(max(gx, 0), J.nx - 1), min(max(gy, 0), J.ny - 1), 0);
     const LT tfill = (LT)J.fill;
     LT v[4];
     uint32_t lp = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+        // indices clamped into the volume: every load stays in range
         const int gz = G.lo[2] + cz0 + u;
-        const uint32_t e = INSIDE ? grow + (uint32_t)(cz0 + u)
-                                  : grow + (uint32_t)min(max(gz, 0), J.nz - 1);
+        const uint32_t e = grow + (uint32_t)min(max(gz, 0), J.nz - 1);
         const T raw = Elem<T>::raw(S.img, e * es, 0);
         const int8_t lab = LBL ? load_i8(S.lbl, e) : lfill;
-        bool in = true;
-        if (!INSIDE)
-            in = row_in && (unsigned)gz < (unsigned)J.nz;
+        const bool in = row_in && (unsigned)gz < (unsigned)J.nz;
         v[u] = in ? (LT)raw : tfill;
         if (LBL)
             lp |= (uint32_t)(uint8_t)(in ? lab : lfill) << (8 * u);
@@ -153,7 +191,7 @@ __device__ __forceinline__ void stage_rows(const FwdJob &J, const Src &S, const 
                                            LT *s_img, int8_t *s_lbl)
 {
     const int ex = G.e[0], ey = G.e[1], P = G.pitch;
-    const int qpr = P >> 2;
+    const int qpr = G.quads;
     const int slab = ey * qpr;
     if (slab <= kThreads) {
         const int ng = kThreads / slab;                    // x-slabs per pass
@@ -209,7 +247,7 @@ __device__ __forceinline__ void stage_footprint(const FwdJob &J, const Src &S, c
     const bool labels = (J.flags & kFlagLabels) != 0;
     const bool inside = G.lo[0] >= 0 && G.lo[1] >= 0 && G.lo[2] >= 0 &&
                         G.lo[0] + G.e[0] <= J.nx && G.lo[1] + G.e[1] <= J.ny &&
-                        G.lo[2] + G.pitch <= J.nz;
+                        G.lo[2] + 4 * G.quads <= J.nz;
     if (inside) {
         if (labels)
             stage_rows<T, LT, true, true>(J, S, G, s_img, s_lbl);
@@ -229,30 +267,36 @@ enum : int { kPathOutside, kPathLdsInterior, kPathLdsBoundary, kPathDirectInteri
 // All runs of one tile along one sampling path.  Each thread owns runs of 4
 // consecutive output voxels along z.
 template <typename T, typename LT, int PATH, bool ALIGNED>
-__device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &TL,
+__device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &SL,
                                          const LT *s_img, const int8_t *s_lbl)
 {
     const Src S = make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz);
     gmut<float> *out = gm<float>(J.out);
     gmut<int8_t> *lout = gm<int8_t>(J.lout);
     gconst<float> *disp = gc<float>(J.disp);
-    const bool labels = (J.flags & kFlagLabels) != 0;
-    const bool vec = (J.flags & kFlagVec) != 0;
-    const Photo P = photo_of(J);
+    Photo P = photo_of(J);
     const int32_t nvox = J.ox * J.oy * J.oz;
-    const int runs_z_log = TL.lz - 2;
-    const int nruns = 1 << (TL.lx + TL.ly + runs_z_log);
+    const int runs_z_log = SL.lz - 2;
+    const int nruns = 1 << (SL.lx + SL.ly + runs_z_log);
     const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
     const int8_t lfill = (int8_t)J.label_fill;
 
     for (int r = threadIdx.x; r < nruns; r += kThreads) {
         const int zr = r & ((1 << runs_z_log) - 1);
         const int rr = r >> runs_z_log;
-        const int y = G.y0 + (rr & ((1 << TL.ly) - 1));
-        const int x = G.x0 + (rr >> TL.ly);
+        const int y = G.y0 + (rr & ((1 << SL.ly) - 1));
+        const int x = G.x0 + (rr >> SL.ly);
         const int z = G.z0 + 4 * zr;
         if (x > G.x1 || y > G.y1 || z > G.z1)
             continue;
+        // The flags are re-read each iteration so that the compiler tests their
+        // bits in SALU where they are used instead of keeping one 64-bit lane
+        // mask per flag live across the loop (scalar register pressure).
+        uint32_t fl = J.flags;
+        asm volatile("" : "+s"(fl));
+        const bool labels = (fl & kFlagLabels) != 0;
+        const bool vec = (fl & kFlagVec) != 0;
+        P.flags = fl;
         const int nvalid = ALIGNED ? 4 : min(4, J.oz - z);
         const uint32_t v0 = (uint32_t)((x * J.oy + y) * J.oz + z);
         float rb[3];
@@ -349,27 +393,55 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
 // LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
 // the LDS reads).
 template <typename T, typename LT, bool ALIGNED>
-__device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling &TL,
-                                            int32_t lds_cells, uint8_t *s_lds)
+__device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, const Tiling &SL,
+                                       uint8_t *s_lds, int32_t lds_cells)
 {
     LT *s_img = reinterpret_cast<LT *>(s_lds);
     int8_t *s_lbl = reinterpret_cast<int8_t *>(s_lds + lds_label_offset<LT>(lds_cells));
-    const TileGeom G = tile_geom(J, t, TL, lds_cells);
     if (G.cls == kOutside) {
-        run_tile<T, LT, kPathOutside, ALIGNED>(J, G, TL, s_img, s_lbl);
+        run_tile<T, LT, kPathOutside, ALIGNED>(J, G, SL, s_img, s_lbl);
     } else if (G.lds) {
         stage_footprint<T, LT>(J, make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz), G, s_img, s_lbl);
         __syncthreads();
         if (G.cls == kInterior)
-            run_tile<T, LT, kPathLdsInterior, ALIGNED>(J, G, TL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsInterior, ALIGNED>(J, G, SL, s_img, s_lbl);
         else
-            run_tile<T, LT, kPathLdsBoundary, ALIGNED>(J, G, TL, s_img, s_lbl);
-        __syncthreads();               // LDS is reused by the next tile
+            run_tile<T, LT, kPathLdsBoundary, ALIGNED>(J, G, SL, s_img, s_lbl);
+        __syncthreads();               // LDS is reused by the next box
     } else if (G.cls == kInterior) {
-        run_tile<T, LT, kPathDirectInterior, ALIGNED>(J, G, TL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectInterior, ALIGNED>(J, G, SL, s_img, s_lbl);
     } else {
-        run_tile<T, LT, kPathDirectBoundary, ALIGNED>(J, G, TL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectBoundary, ALIGNED>(J, G, SL, s_img, s_lbl);
     }
+}
+
+// One output tile, processed as sub-tiles of the job's sub-tile shape (the
+// whole tile unless its input footprint would not fit the LDS reservation).
+// ALIGNED: the output z extent is a multiple of 4, so every run is one noise
+// group and (with 16-byte aligned outputs) one vector store.  LT: type of the
+// LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
+// the LDS reads).
+template <typename T, typename LT, bool ALIGNED>
+__device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling &TL,
+                                            int32_t lds_cells, uint8_t *s_lds)
+{
+    const int tz = t % J.tiles_z;
+    const int rest = t / J.tiles_z;
+    const int ty = rest % J.tiles_y;
+    const int tx = rest / J.tiles_y;
+    const int x0 = tx << TL.lx, y0 = ty << TL.ly, z0 = tz << TL.lz;
+    const int x1 = min(x0 + (1 << TL.lx), J.ox) - 1;
+    const int y1 = min(y0 + (1 << TL.ly), J.oy) - 1;
+    const int z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
+    const Tiling SL = {J.sub[0], J.sub[1], J.sub[2]};
+    for (int sx = x0; sx <= x1; sx += 1 << SL.lx)
+        for (int sy = y0; sy <= y1; sy += 1 << SL.ly)
+            for (int sz = z0; sz <= z1; sz += 1 << SL.lz) {
+                const TileGeom G = box_geom(J, sx, sy, sz, min(sx + (1 << SL.lx) - 1, x1),
+                                            min(sy + (1 << SL.ly) - 1, y1),
+                                            min(sz + (1 << SL.lz) - 1, z1), lds_cells);
+                fwd_box<T, LT, ALIGNED>(J, G, SL, s_lds, lds_cells);
+            }
 }
 
 template <typename T, bool ALIGNED>
@@ -428,7 +500,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
     }
 }
 
-// Upper bound on the footprint cells of any tile of job J (see tile_geom).
+// Upper bound on the footprint cells of any tile of job J (see box_geom).
 int32_t footprint_cells_bound(const FwdJob &J, const Tiling &TL)
 {
     const int t[3] = {1 << TL.lx, 1 << TL.ly, 1 << TL.lz};
@@ -441,12 +513,44 @@ int32_t footprint_cells_bound(const FwdJob &J, const Tiling &TL)
         int64_t e = std::min<int64_t>((int64_t)std::floor(span) + 3, (int64_t)n[i] + 2);
         e = std::max<int64_t>(e, 1);
         if (i == 2)
-            e = (e + 3) & ~(int64_t)3;       // LDS row pitch
+            e = lds_pitch((int32_t)e);       // LDS row pitch
         cells *= e;
         if (cells > (int64_t)1 << 30)
             return 1 << 30;
     }
     return (int32_t)cells;
+}
+
+// Sub-tile shape of job J for tile TL and an LDS reservation of lds_cells
+// cells: the whole tile when its footprint bound fits; otherwise the sub-box
+// of the tile with the most voxels (at least 2^10, or the tile's own count if
+// smaller; z extent >= 4) whose bound fits, fewest cells per voxel among
+// equals; the whole tile (direct gathers) when none fits.
+Tiling choose_subtile(const FwdJob &J, const Tiling &TL, int32_t lds_cells)
+{
+    if (J.disp || lds_cells <= 0 || footprint_cells_bound(J, TL) <= lds_cells)
+        return TL;
+    const int min_log = std::min(10, TL.lx + TL.ly + TL.lz);
+    Tiling best = TL;
+    int best_log = -1;
+    double best_ratio = 0.0;
+    for (int a = 0; a <= TL.lx; ++a)
+        for (int b = 0; b <= TL.ly; ++b)
+            for (int c = 2; c <= TL.lz; ++c) {
+                if (a + b + c < min_log)
+                    continue;
+                const Tiling S = {a, b, c};
+                const int32_t cells = footprint_cells_bound(J, S);
+                if (cells > lds_cells)
+                    continue;
+                const double ratio = (double)cells / (double)(1 << (a + b + c));
+                if (a + b + c > best_log || (a + b + c == best_log && ratio < best_ratio)) {
+                    best = S;
+                    best_log = a + b + c;
+                    best_ratio = ratio;
+                }
+            }
+    return best;
 }
 
 int32_t lds_cells_cap(int32_t elem_bytes)
@@ -474,19 +578,24 @@ hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s)
     const int32_t cells = J.disp ? 0 : lds_cells_for(footprint_cells_bound(J, TL), esz);
     const size_t lds = lds_bytes_for(cells, esz);
     const bool aligned = J.oz % 4 == 0;
+    FwdJob Js = J;
+    const Tiling SL = choose_subtile(J, TL, cells);
+    Js.sub[0] = SL.lx;
+    Js.sub[1] = SL.ly;
+    Js.sub[2] = SL.lz;
     if (J.dtype == kI16) {
         if (aligned)
             hipLaunchKernelGGL((k_warp_single<int16_t, true>), dim3(grid), dim3(kThreads), lds, s,
-                               J, TL, ntiles, cells);
+                               Js, TL, ntiles, cells);
         else
             hipLaunchKernelGGL((k_warp_single<int16_t, false>), dim3(grid), dim3(kThreads), lds, s,
-                               J, TL, ntiles, cells);
+                               Js, TL, ntiles, cells);
     } else {
         if (aligned)
-            hipLaunchKernelGGL((k_warp_single<float, true>), dim3(grid), dim3(kThreads), lds, s, J,
+            hipLaunchKernelGGL((k_warp_single<float, true>), dim3(grid), dim3(kThreads), lds, s, Js,
                                TL, ntiles, cells);
         else
-            hipLaunchKernelGGL((k_warp_single<float, false>), dim3(grid), dim3(kThreads), lds, s, J,
+            hipLaunchKernelGGL((k_warp_single<float, false>), dim3(grid), dim3(kThreads), lds, s, Js,
                                TL, ntiles, cells);
     }
     return hipGetLastError();

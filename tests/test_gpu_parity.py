@@ -408,8 +408,13 @@ def test_batch_plan_matches_single_calls_and_oracle():
 
 @pytest.mark.parametrize("tile,wg,lds,fmt", [((4, 8, 32), 0, 0, 0), ((8, 8, 16), 2, 0, 1),
                                              ((2, 4, 64), 1, 2048, 0), ((16, 16, 16), 4, 0, 1),
-                                             ((8, 16, 16), 0, -1, 0), ((8, 8, 8), 0, 300, 1)])
+                                             ((8, 16, 16), 0, -1, 0), ((8, 8, 8), 0, 300, 1),
+                                             ((16, 16, 16), 0, 6000, 0), ((16, 16, 16), 2, 8000, 1),
+                                             ((32, 16, 16), 0, 3000, 0)])
 def test_batch_launch_shapes_bit_identical(tile, wg, lds, fmt):
+    """Every launch shape gives the single-call result bit for bit, including
+    reservations too small for a whole tile's footprint (tiles staged in
+    sub-tiles, or gathered directly)."""
     T = _batch_jobs(n=3, out_dim=(36, 30, 44))
     jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
             for (j, M, img, lbl, out, lout) in T]
