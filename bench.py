@@ -35,6 +35,28 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 C3_OUT = (120, 120, 160)
+# Launch shape of the batched kernel (tile, workgroups per CU, LDS cells,
+# LDS cell format), the fastest in sweeps over tile shapes and LDS
+# reservations on this workload; --autotune re-runs the sweep.
+C3_TUNING = ((16, 16, 16), 0, 8176, 0)
+
+# VALU roofline.  Peak: 256 CUs x 64 lanes x 2.4 GHz non-packed lane-ops
+# (one FP32/INT32 op per lane per cycle; transcendentals and 32x32->64-bit
+# multiplies issue at quarter rate and are counted as 4).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Lane-ops the method's arithmetic needs (not the kernel's instruction count):
+#  sampled voxel: coordinate 3 FMA; trilinear 3 floor + 3 fraction + 7 lerps x 2;
+#    base-cell index 3 conversions + 2 multiply-adds + 1 add; label 3 add + 3
+#    floor + 3 conversions + 3 index; one int16 conversion            = 42
+#  every voxel, photometrics: gain/offset FMA, noise FMA, window 4
+#    (sub, mul, max, min), gamma log2 + mul + exp2 (4 + 1 + 4)         = 15
+#  every voxel, noise: Philox4x32-10 per 4 voxels, 10 rounds of 2 64-bit
+#    products (4 each) + 2 three-input XOR = 100 / 4 = 25; Box-Muller per
+#    pair 2 x (shift, convert, fma) + log2 4 + mul + sqrt 4 + sin 4 + cos 4
+#    + 2 mul = 25 / 2 = 12.5                                            = 37.5
+OPS_SAMPLED = 42.0
+OPS_PHOTO = 15.0
+OPS_NOISE = 37.5
 
 
 def log(msg):
@@ -42,9 +64,10 @@ def log(msg):
 
 
 def source_hash():
+    """Hash of the sources the batched forward kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1811_11226_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("device_common.h", "warp_fwd.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -83,6 +106,7 @@ def touched_counts(in_dim, out_dim, M, dev):
     n = torch.tensor(in_dim, dtype=torch.float64, device=dev)
     img_mark = torch.zeros(int(in_dim[0] * in_dim[1] * in_dim[2]), dtype=torch.bool, device=dev)
     lbl_mark = torch.zeros_like(img_mark)
+    sampled = 0
     X, Y, Z = out_dim
     ys, zs = torch.meshgrid(torch.arange(Y, device=dev, dtype=torch.float64),
                             torch.arange(Z, device=dev, dtype=torch.float64), indexing="ij")
@@ -94,6 +118,7 @@ def touched_counts(in_dim, out_dim, M, dev):
                          ys.repeat(xs.numel()), zs.repeat(xs.numel())])
         q = A[:, :3] @ P + A[:, 3:4]
         guard = ((q > -1) & (q < n[:, None])).all(0)
+        sampled += int(guard.sum().item())
         q = q[:, guard]
         f = torch.floor(q)
         t = q - f
@@ -110,7 +135,7 @@ def touched_counts(in_dim, out_dim, M, dev):
         j = torch.floor(q + 0.5).to(torch.int64)
         ok = ((j >= 0) & (j < n.to(torch.int64)[:, None])).all(0)
         lbl_mark[(j[:, ok] * strides[:, None]).sum(0)] = True
-    return int(img_mark.sum().item()), int(lbl_mark.sum().item())
+    return int(img_mark.sum().item()), int(lbl_mark.sum().item()), sampled
 
 
 # ---------------------------------------------------------------------------
@@ -121,7 +146,7 @@ class C3Set:
     """One 16-volume input batch resident in HBM with its outputs, a batch
     plan, and a pool of parameter draws."""
 
-    def __init__(self, batch, n_pool, dev, tile=None, wg=0):
+    def __init__(self, batch, n_pool, dev, tuning=C3_TUNING):
         import numpy as np
         import torch
 
@@ -153,7 +178,8 @@ class C3Set:
                                  fill=j.fill, label_fill=j.label_fill, photo=ph)
                   for k, (j, (M, ph)) in enumerate(zip(self.jobs, entry))]
             self.job_arrays.append(cj)
-        self.plan = ctaug.BatchPlan(self.job_arrays[0], tile=tile, wg_per_cu=wg)
+        self.plan = ctaug.BatchPlan(self.job_arrays[0], tile=tuning[0], wg_per_cu=tuning[1],
+                                    lds_cells=tuning[2], lds_format=tuning[3])
 
     def voxels(self):
         return len(self.jobs) * C3_OUT[0] * C3_OUT[1] * C3_OUT[2]
@@ -171,16 +197,17 @@ def run_c3(args, dev):
     log(f"c3: inputs resident ({time.time() - t0:.1f} s)")
     stream = torch.cuda.Stream()
 
-    # autotune the launch shape on batch 0, then give every plan the winner
-    cands = [(tile, wg, lds, fmt) for tile in [(8, 8, 16), (8, 16, 16), (16, 16, 16), (8, 8, 32),
-                                               (4, 16, 16)]
-             for wg in (0, 2) for lds in (0, 12272) for fmt in (0, 1)]
-    with torch.cuda.stream(stream):
-        best, times = sets[0].plan.autotune(cands, reps=3)
-    order = sorted(range(len(cands)), key=lambda i: times[i])
-    log(f"c3: autotune best {best} ({min(times):.3f} ms); top 5 "
-        f"{[(cands[i], round(times[i], 3)) for i in order[:5]]}")
-    for s in sets[1:]:
+    best, times = C3_TUNING, None
+    if args.autotune:
+        # sweep launch shapes on batch 0, then give every plan the winner
+        cands = [(tile, 0, lds, fmt) for tile in [(8, 16, 16), (16, 16, 16), (16, 16, 32)]
+                 for lds in (0, 6128, 8176, 12272) for fmt in (0, 1)]
+        with torch.cuda.stream(stream):
+            best, times = sets[0].plan.autotune(cands, reps=3)
+        order = sorted(range(len(cands)), key=lambda i: times[i])
+        log(f"c3: autotune best {best} ({min(times):.3f} ms); top 5 "
+            f"{[(cands[i], round(times[i], 3)) for i in order[:5]]}")
+    for s in sets:
         s.plan.close()
         s.plan = ctaug.BatchPlan(s.job_arrays[0], tile=best[0], wg_per_cu=best[1],
                                  lds_cells=best[2], lds_format=best[3])
@@ -237,20 +264,25 @@ def run_c3(args, dev):
 
     # algorithmic bytes of the timed kernel-only launches (pool-0 draws)
     t0 = time.time()
-    bytes_per_set = []
+    bytes_per_set, ops_per_set = [], []
     touched = []
+    nv = C3_OUT[0] * C3_OUT[1] * C3_OUT[2]
     for s in sets:
-        b = 0
+        b = ops = 0
         for k, j in enumerate(s.jobs):
-            ti, tl = touched_counts(j.in_dim, C3_OUT, s.pool[0][k][0], dev)
-            touched.append(ti / (C3_OUT[0] * C3_OUT[1] * C3_OUT[2]))
-            b += C3_OUT[0] * C3_OUT[1] * C3_OUT[2] * (4 + 1) + ti * 2 + tl * 1
+            ti, tl, ns = touched_counts(j.in_dim, C3_OUT, s.pool[0][k][0], dev)
+            touched.append(ti / nv)
+            b += nv * (4 + 1) + ti * 2 + tl * 1
+            ops += ns * OPS_SAMPLED + nv * (OPS_PHOTO + OPS_NOISE)
         bytes_per_set.append(b)
+        ops_per_set.append(ops)
     alg_bytes = float(np.mean(bytes_per_set))
+    alg_ops = float(np.mean(ops_per_set))
     log(f"c3: algorithmic bytes per launch {alg_bytes / 1e6:.1f} MB "
         f"(mean touched fraction f = {np.mean(touched):.3f}; {time.time() - t0:.1f} s)")
-    return dict(sets=sets, step_ms=step_ms, kern_ms=kern_ms, alg_bytes=alg_bytes, tuning=best,
-                tune_ms=times, voxels=sets[0].voxels(), stream=stream)
+    log(f"c3: algorithmic lane-ops per launch {alg_ops / 1e9:.3f} G")
+    return dict(sets=sets, step_ms=step_ms, kern_ms=kern_ms, alg_bytes=alg_bytes, alg_ops=alg_ops,
+                tuning=best, tune_ms=times, voxels=sets[0].voxels(), stream=stream)
 
 
 # ---------------------------------------------------------------------------
@@ -283,7 +315,7 @@ def run_c2(dev, stream, reps):
     lout = torch.empty(j.out_dim, dtype=torch.int8, device=dev)
     ms = time_loop(lambda: ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo, out=out,
                                              lbl_out=lout), reps, stream)
-    ti, tl = touched_counts(j.in_dim, j.out_dim, M, dev)
+    ti, tl, _ = touched_counts(j.in_dim, j.out_dim, M, dev)
     nv = out.numel()
     alg = nv * 5 + ti * 2 + tl
     return {"workload": "512x512x320 int16 + int8 labels -> f32 + int8, full photometrics",
@@ -384,21 +416,75 @@ def copy_bandwidth(dev, stream, nbytes=1 << 30, reps=10):
 # CPU baseline: the oracle, as it stands, on this host's cores
 # ---------------------------------------------------------------------------
 
-def cpu_baseline(sets):
+def cpu_baseline(sets, min_seconds=10.0):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     s = sets[0]
     nv = 0
+    passes = 0
     t0 = time.perf_counter()
-    for k, j in enumerate(s.jobs):
-        M, ph = s.pool[0][k]
-        oracle.warp(j.img, M, C3_OUT, lbl=j.lbl, fill=j.fill, label_fill=j.label_fill, photo=ph)
-        nv += C3_OUT[0] * C3_OUT[1] * C3_OUT[2]
+    while passes == 0 or time.perf_counter() - t0 < min_seconds:
+        for k, j in enumerate(s.jobs):
+            M, ph = s.pool[0][k]
+            oracle.warp(j.img, M, C3_OUT, lbl=j.lbl, fill=j.fill, label_fill=j.label_fill,
+                        photo=ph)
+            nv += C3_OUT[0] * C3_OUT[1] * C3_OUT[2]
+        passes += 1
     dt = time.perf_counter() - t0
     return {"value": round(nv / dt / 1e9, 5), "unit": "Gvoxel/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"the full 16-volume batch once ({nv / 1e6:.1f} Mvoxel out), "
-                      f"{dt:.2f} s wall, OpenMP over x-slabs, FP64"}
+            "sample": f"the 16-volume batch {passes}x ({nv / 1e6:.1f} Mvoxel out), {dt:.2f} s "
+                      f"wall, oracle in parity mode (FP32-pinned coordinates, FP64 "
+                      f"interpolation), OpenMP over x-slabs"}
+
+
+def write_traffic(fetch_csv, write_csv, copy_bytes=1 << 30):
+    """Summarise two rocprofv3 --pmc runs of `bench.py --profile` (FETCH_SIZE,
+    then WRITE_SIZE) into profiles/warp_batch_c3_traffic.txt: per-dispatch KiB of
+    the batched kernel, scaled by what the same counter reads for the copy
+    kernel moving copy_bytes each way."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                key = "batch" if "k_warp_batch" in name else "copy" if "k_copy16" in name else None
+                if key:
+                    vals.setdefault(key, []).append(float(r["Counter_Value"]))
+        return vals
+
+    fv, wv = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    mean = lambda v: sum(v) / len(v)
+    f_scale = mean(fv["copy"]) * 1024.0 / copy_bytes
+    w_scale = mean(wv["copy"]) * 1024.0 / copy_bytes
+    fetch = mean(fv["batch"]) * 1024.0 / f_scale
+    write = mean(wv["batch"]) * 1024.0 / w_scale
+    path = os.path.join(ROOT, "profiles", "warp_batch_c3_traffic.txt")
+    with open(path, "w") as f:
+        f.write("# HBM-side traffic of k_warp_batch on the 16-volume 120x120x160 batch\n")
+        f.write("# (cd /tmp && export TMPDIR=/tmp)\n")
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            f.write(f"# rocprofv3 --pmc {c} --kernel-include-regex 'k_warp_batch|k_copy16' "
+                    f"--output-format csv -d <dir> -o run -- python3 bench.py --profile "
+                    f"--steps 20 --warmup 2\n")
+        f.write("# python3 bench.py --traffic <FETCH_SIZE dir>/run_counter_collection.csv "
+                "<WRITE_SIZE dir>/run_counter_collection.csv\n")
+        f.write("# KiB per dispatch (mean over the batched kernel's dispatches) scaled by\n")
+        f.write("# what the same counter reads for the copy kernel moving 1 GiB each way\n")
+        f.write(f"batch_dispatches = {len(fv['batch'])}\n")
+        f.write(f"fetch_kib_raw = {mean(fv['batch']):.1f}\n")
+        f.write(f"write_kib_raw = {mean(wv['batch']):.1f}\n")
+        f.write(f"copy_fetch_scale = {f_scale:.4f}\n")
+        f.write(f"copy_write_scale = {w_scale:.4f}\n")
+        f.write(f"fetch_bytes_per_launch = {fetch:.0f}\n")
+        f.write(f"write_bytes_per_launch = {write:.0f}\n")
+        f.write(f"hbm_bytes_per_launch = {fetch + write:.0f}\n")
+        f.write(f"source_sha256 = {source_hash()}\n")
+    print(path)
 
 
 def main():
@@ -410,7 +496,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: headline workload + copy reference only")
+    ap.add_argument("--autotune", action="store_true",
+                    help="sweep launch shapes instead of the fixed C3_TUNING")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/warp_batch_c3_traffic.txt from two rocprofv3 --pmc "
+                         "counter_collection.csv files and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic:
+        write_traffic(*args.traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (each volume of a batch is "
               "independent; a multi-GPU run would shard volumes across GPUs with no exchange)",
@@ -434,7 +528,8 @@ def main():
     copy_gbs = copy_bandwidth(dev, stream)
     log(f"copy reference kernel: {copy_gbs:.0f} GB/s")
     value = r["voxels"] / (r["step_ms"] * 1e-3) / 1e9
-    achieved = r["alg_bytes"] / (r["kern_ms"] * 1e-3) / 1e9
+    hbm_gbs = r["alg_bytes"] / (r["kern_ms"] * 1e-3) / 1e9
+    achieved = r["alg_ops"] / (r["kern_ms"] * 1e-3) / 1e12
     traffic = stored_traffic("warp_batch_c3")
     result = {
         "metric": "augmented Gvoxel/s + % HBM peak (fwd, fwd+bwd) at 1 GPU vs CPU oracle",
@@ -464,15 +559,18 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(ALU_PEAK_TOPS, 2),
+            "unit": "TOP/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 4),
+            "traffic": None if traffic is None else int(traffic),
             "kernel": "k_warp_batch",
             "kernel_ms": round(r["kern_ms"], 5),
+            "algorithmic_ops_per_launch": int(r["alg_ops"]),
             "algorithmic_bytes_per_launch": int(r["alg_bytes"]),
+            "hbm_achieved_GBs": round(hbm_gbs, 1),
+            "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
             "copy_kernel_GBs": round(copy_gbs, 1),
         },
     }

@@ -63,7 +63,8 @@ typedef enum {
 } ctaug_dtype;
 
 /* A dense volume.  data: device pointer; dim: X, Y, Z (each >= 0).
- * Element counts up to 2^31 - 1 per volume are supported. */
+ * Element counts up to 2^31 - 1 per volume are supported (FP32 input images:
+ * up to 2^30 - 1, so that their byte size fits a 32-bit buffer range). */
 typedef struct {
     void *data;
     int32_t dtype;         /* ctaug_dtype */

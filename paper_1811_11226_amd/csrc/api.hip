@@ -16,6 +16,7 @@ using namespace ctaug;
 namespace {
 
 constexpr int64_t kMaxElems = 2147483647LL;   // int32 linear indices in the kernels
+constexpr int64_t kMaxF32In = 1073741823LL;   // FP32 input bytes must fit a 32-bit buffer range
 constexpr Tiling kDefaultTiling = {3, 4, 4};   // 8 x 16 x 16 output voxels per workgroup
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -147,6 +148,8 @@ ctaug_status make_job(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const fl
     ctaug_status st;
     if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
         return st;
+    if (img_in->dtype == CTAUG_F32 && nelem(img_in->dim) > kMaxF32In)
+        return CTAUG_ESHAPE;
     if ((st = check_vol(img_out, 1u << CTAUG_F32)) != CTAUG_OK)
         return st;
     if (lbl_in) {

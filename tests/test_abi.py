@@ -173,6 +173,8 @@ def test_warp_rejects_bad_arguments(L):
     assert warp(L, img, None, M, 0.0, 0, None, vol((4, 4, 4), I16), None) == EDTYPE
     assert warp(L, vol((8, -1, 8), I16), None, M, 0.0, 0, None, out, None) == ESHAPE
     assert warp(L, vol((1 << 16, 1 << 16, 1), I16), None, M, 0.0, 0, None, out, None) == ESHAPE
+    assert warp(L, vol((1 << 10, 1 << 10, 1 << 10), F32), None, M, 0.0, 0, None, out,
+                None) == ESHAPE
     assert warp(L, vol((8, 8, 8), I16, data=None), None, M, 0.0, 0, None, out, None) == EINVAL
     # labels: dtype, dims, missing output
     assert warp(L, img, vol((8, 8, 8), F32), M, 0.0, 0, None, out, lout) == EDTYPE
