@@ -379,7 +379,7 @@ extern "C" size_t ctaug_warp_backward_workspace(const int64_t out_dim[3])
 {
     if (!out_dim || !dims_valid(out_dim))
         return 0;
-    return (size_t)bwd_num_tiles(out_dim[0], out_dim[1], out_dim[2]) * 12 * sizeof(double);
+    return (size_t)bwd_partial_rows(out_dim[0], out_dim[1], out_dim[2]) * 12 * sizeof(double);
 }
 
 static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], const float *disp,
@@ -509,6 +509,7 @@ struct ctaug_batch_plan {
     int32_t lds_cells = 0;              // LDS footprint cells reserved per workgroup
     int32_t elem_bytes = 4;             // LDS cell width: 2 when int16 cells are used
     bool all_i16 = true;                // every job has an int16 input
+    bool all_f32 = true;                // every job has an FP32 input
     bool aligned = true;                // every job's output z extent is a multiple of 4
     int num_cu = 256;
     hipEvent_t upload_done = nullptr;
@@ -614,6 +615,13 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     return CTAUG_OK;
 }
 
+int batch_mode(const ctaug_batch_plan *p)
+{
+    if (p->all_i16)
+        return p->elem_bytes == 2 ? kBatchI16I16 : kBatchI16F32;
+    return p->all_f32 ? kBatchF32 : kBatchMixed;
+}
+
 ctaug_status enqueue(ctaug_batch_plan *p, hipStream_t s)
 {
     if (hipMemcpyAsync(p->table, p->staging, sizeof(FwdJob) * p->n, hipMemcpyHostToDevice, s) !=
@@ -621,7 +629,7 @@ ctaug_status enqueue(ctaug_batch_plan *p, hipStream_t s)
         return CTAUG_EHIP;
     return hip_status(
         launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL, p->lds_cells,
-                          p->elem_bytes, p->aligned, s));
+                          p->elem_bytes, batch_mode(p), p->aligned, s));
 }
 
 }  // namespace
@@ -670,6 +678,8 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
         p->aligned = p->aligned && p->jobs[i].oz % 4 == 0;
         if (p->jobs[i].dtype != CTAUG_I16)
             p->all_i16 = false;
+        if (p->jobs[i].dtype != CTAUG_F32)
+            p->all_f32 = false;
     }
     int dev = 0;
     hipDeviceProp_t prop;
@@ -711,6 +721,9 @@ extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug
             return CTAUG_ESHAPE;
         if (next[i].dtype != CTAUG_I16 && p->elem_bytes < 4)
             return CTAUG_EDTYPE;           // the LDS reservation was sized for int16 cells
+        if ((p->all_i16 && next[i].dtype != CTAUG_I16) ||
+            (p->all_f32 && next[i].dtype != CTAUG_F32))
+            return CTAUG_EDTYPE;           // the launch was specialised for the creation dtypes
     }
     if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
         return CTAUG_EHIP;
@@ -743,7 +756,7 @@ extern "C" ctaug_status ctaug_batch_plan_run(ctaug_batch_plan *p, void *stream)
     if (!p || !p->upload_recorded)
         return CTAUG_EINVAL;
     return hip_status(launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL,
-                                        p->lds_cells, p->elem_bytes, p->aligned,
+                                        p->lds_cells, p->elem_bytes, batch_mode(p), p->aligned,
                                         as_stream(stream)));
 }
 

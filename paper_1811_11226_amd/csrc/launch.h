@@ -9,9 +9,12 @@
 namespace ctaug {
 
 hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s);
+// Input / LDS cell types shared by every job of a batch launch.
+enum : int { kBatchMixed = 0, kBatchI16F32 = 1, kBatchI16I16 = 2, kBatchF32 = 3 };
 hipError_t launch_warp_batch(const FwdJob *jobs_dev, const int32_t *prefix_dev, int32_t njobs,
                              int32_t total_tiles, int32_t grid, const Tiling &TL,
-                             int32_t lds_cells, int32_t elem_bytes, bool aligned, hipStream_t s);
+                             int32_t lds_cells, int32_t elem_bytes, int mode, bool aligned,
+                             hipStream_t s);
 // Largest LDS footprint (cells of input-type image + int8 label) any tile of J
 // can need; the most cells a reservation of elem_bytes-wide cells can hold;
 // the cells reserved for a bound; the LDS bytes of a reservation.
@@ -28,7 +31,7 @@ hipError_t launch_noise(uint64_t v0, int64_t n, uint32_t vol, uint32_t k0, uint3
 hipError_t launch_box_muller(const uint32_t *words, int64_t npairs, float *out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
-int64_t bwd_num_tiles(int64_t ox, int64_t oy, int64_t oz);
+int64_t bwd_partial_rows(int64_t ox, int64_t oy, int64_t oz);
 hipError_t launch_warp_bwd(const FwdJob &J, const float *g, float *g_img, float *g_disp,
                            double *g_M, double *partials, hipStream_t s);
 

@@ -339,6 +339,46 @@ def test_affine_backward_parity(dims, dtype):
     assert_grad(_np(g_M), r_M, "g_M")
 
 
+@pytest.mark.parametrize("in_dim,out_dim,scale,dtype", [
+    ((264, 128, 64), (264, 128, 64), (0.8, 1.2), np.float32),   # > 2048 tiles: strided WGs
+    ((120, 100, 80), (30, 25, 20), (3.5, 4.0), np.int16),       # footprints beyond LDS
+    ((40, 36, 30), (70, 60, 52), (0.45, 0.55), np.float32),     # upsampling, tiny footprints
+])
+def test_affine_backward_tiles_and_footprints(in_dim, out_dim, scale, dtype):
+    """Image and parameter adjoints across persistent tile striding, tiles
+    whose footprint exceeds the LDS reservation (global atomics), and
+    crops with out-of-volume tiles."""
+    rng = np.random.default_rng(int(in_dim[0]))
+    img, _ = phantom_pair(in_dim, seed=8)
+    prm = draw_affine_params(rng, AugmentRanges(scale=scale), in_dim, out_dim)
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    g = rng.standard_normal(out_dim).astype(np.float32)
+    g_img, g_M = ctaug.warp_affine_backward(_t(img.astype(dtype)), M, _t(g))
+    r_img, r_M, _ = oracle.warp_backward(img, M, g)
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
+
+
+def test_affine_backward_param_only_and_singular_map():
+    """grad_M alone (output-tiled kernel) and a singular A (no inverse map:
+    the image adjoint falls back to per-corner atomics) against the oracle."""
+    rng = np.random.default_rng(21)
+    dims = (40, 36, 44)
+    img, _ = phantom_pair(dims, seed=3)
+    g = rng.standard_normal(dims).astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    _, g_M = ctaug.warp_affine_backward(_t(img), M, _t(g), want_img=False)
+    _, r_M, _ = oracle.warp_backward(img, M, g, want_img=False)
+    assert_grad(_np(g_M), r_M, "g_M only")
+    S = np.array([[0.5, 0.25, 0.0, 12.0], [0.0, 1.0, 0.0, 3.0], [1.0, 0.5, 0.0, 7.5]],
+                 dtype=np.float32).ravel()         # rank 2: z does not move the sample
+    g_img, g_M = ctaug.warp_affine_backward(_t(img), S, _t(g))
+    r_img, r_M, _ = oracle.warp_backward(img, S, g)
+    assert_grad(_np(g_img), r_img, "g_img singular")
+    assert_grad(_np(g_M), r_M, "g_M singular")
+
+
 def test_affine_backward_adjoint_identity_gpu():
     rng = np.random.default_rng(10)
     dims = (40, 40, 40)
