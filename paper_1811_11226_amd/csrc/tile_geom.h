@@ -93,10 +93,6 @@ __device__ __forceinline__ TileGeom box_geom(const FwdJob &J, int x0, int y0, in
     return G;
 }
 
-// Footprint rows are quads of 4 cells.  When one x-slab of the footprint
-// (ey rows of quads_per_row quads) fits the workgroup, each lane keeps one
-// fixed (y row, quad) for the whole tile and walks the x-slabs: the row
-// bookkeeping is two additions per quad.  Larger slabs use a generic loop.
 __device__ __forceinline__ void store4(float *dst, const float v[4])
 {
     *reinterpret_cast<f32x4 *>(dst) = f32x4{v[0], v[1], v[2], v[3]};
@@ -134,31 +130,41 @@ __device__ __forceinline__ void copy_quad(rsrc_t r, uint32_t off, float *dst, in
               (float)(int16_t)(w.y & 0xffffu), (float)((int32_t)w.y >> 16)};
 }
 
-template <typename T, typename LT, bool INSIDE, bool LBL>
-__device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, const TileGeom &G,
-                                           int gx, int gy, int cz0, uint32_t grow_inside,
+// floor(a / b) for 0 <= a < 2^24, 0 < b < 2^16: FP32 reciprocal estimate and
+// one integer correction step.
+__device__ __forceinline__ int div_small(int a, int b, float rcp_b)
+{
+    int q = (int)((float)a * rcp_b);
+    const int r = a - q * b;
+    q += (r >= b) - (r < 0);
+    return q;
+}
+
+// One quad of the footprint: input cells (gx, gy, gz0 .. gz0 + 3).  A quad
+// wholly inside the volume is copied with one wide load per array; a quad at
+// the volume's edge loads each cell from its index clamped into the volume
+// (every load stays in range) and substitutes fill / label_fill outside.
+template <typename T, typename LT, bool LBL>
+__device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, int gx, int gy, int gz0,
                                            LT *dst, int8_t *ldst)
 {
     constexpr uint32_t es = sizeof(T);
-    if (INSIDE) {
-        // every cell of the quad lies in the volume: one load per array
-        const uint32_t e = grow_inside + (uint32_t)cz0;
-        copy_quad(S.img, e * es, dst + cz0, T());
+    const bool row_in = (unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny;
+    if (row_in && gz0 >= 0 && gz0 + 3 < J.nz) {
+        const uint32_t e = elem_index(S, gx, gy, gz0);
+        copy_quad(S.img, e * es, dst, T());
         if (LBL)
-            *reinterpret_cast<uint32_t *>(ldst + cz0) =
-                __builtin_amdgcn_raw_buffer_load_b32(S.lbl, e, 0, 0);
+            *reinterpret_cast<uint32_t *>(ldst) = __builtin_amdgcn_raw_buffer_load_b32(S.lbl, e, 0, 0);
         return;
     }
     const int8_t lfill = (int8_t)J.label_fill;
-    const bool row_in = (unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny;
     const uint32_t grow = elem_index(S, min(max(gx, 0), J.nx - 1), min(max(gy, 0), J.ny - 1), 0);
     const LT tfill = (LT)J.fill;
     LT v[4];
     uint32_t lp = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        // indices clamped into the volume: every load stays in range
-        const int gz = G.lo[2] + cz0 + u;
+        const int gz = gz0 + u;
         const uint32_t e = grow + (uint32_t)min(max(gz, 0), J.nz - 1);
         const T raw = Elem<T>::raw(S.img, e * es, 0);
         const int8_t lab = LBL ? load_i8(S.lbl, e) : lfill;
@@ -167,84 +173,43 @@ __device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, const 
         if (LBL)
             lp |= (uint32_t)(uint8_t)(in ? lab : lfill) << (8 * u);
     }
-    store4(dst + cz0, v);
+    store4(dst, v);
     if (LBL)
-        *reinterpret_cast<uint32_t *>(ldst + cz0) = lp;
+        *reinterpret_cast<uint32_t *>(ldst) = lp;
 }
 
-template <typename T, typename LT, bool INSIDE, bool LBL>
-__device__ __forceinline__ void stage_rows(const FwdJob &J, const Src &S, const TileGeom &G,
-                                           LT *s_img, int8_t *s_lbl)
+// Copy the tile's input footprint into LDS in the LDS cell type (labels as
+// int8), with fill / label_fill in cells outside the volume.  The footprint is
+// e[0] x e[1] rows of `quads` quads of 4 cells (row pitch G.pitch cells); the
+// workgroup's lanes take the quads in flat order, so every lane is busy
+// whatever the row length.
+template <typename T, typename LT, bool LBL>
+__device__ __forceinline__ void stage_quads(const FwdJob &J, const Src &S, const TileGeom &G,
+                                            LT *s_img, int8_t *s_lbl)
 {
-    const int ex = G.e[0], ey = G.e[1], P = G.pitch;
-    const int qpr = G.quads;
-    const int slab = ey * qpr;
-    if (slab <= kThreads) {
-        const int ng = kThreads / slab;                    // x-slabs per pass
-        const int g = threadIdx.x / slab;
-        const int s = threadIdx.x - g * slab;
-        if (g >= ng)
-            return;
-        const int cy = s / qpr;
-        const int cz0 = 4 * (s - cy * qpr);
-        const int gy = G.lo[1] + cy;
-        // element index of (lo_x + cx, gy, lo_z): advanced by ng x-planes per pass
-        const uint32_t plane = mul24((uint32_t)S.ny, (uint32_t)S.nz);
-        uint32_t grow = INSIDE ? elem_index(S, G.lo[0] + g, gy, G.lo[2]) : 0u;
-        const uint32_t gstep = mul24((uint32_t)ng, plane);
-        const int lstep = ng * ey * P;
-        int loff = (g * ey + cy) * P;
-#pragma unroll 4
-        for (int cx = g; cx < ex; cx += ng) {
-            stage_quad<T, LT, INSIDE, LBL>(J, S, G, G.lo[0] + cx, gy, cz0, grow, s_img + loff,
-                                       s_lbl + loff);
-            grow += gstep;
-            loff += lstep;
-        }
-        return;
-    }
-    // generic: lanes x rows
-    const int quads = qpr;
-    const int lr_log = quads <= 4 ? 2 : quads <= 8 ? 3 : quads <= 16 ? 4 : quads <= 32 ? 5 : 6;
-    const int LR = 1 << lr_log;
-    const int rpi = kThreads >> lr_log;
-    const int lane_q = threadIdx.x & (LR - 1);
-    const int rows = ex * ey;
-    for (int r = threadIdx.x >> lr_log; r < rows; r += rpi) {
-        const int cx = r / ey;
-        const int cy = r - cx * ey;
-        const int gx = G.lo[0] + cx, gy = G.lo[1] + cy;
-        const uint32_t grow = INSIDE ? elem_index(S, gx, gy, G.lo[2]) : 0u;
-        for (int q = lane_q; q < quads; q += LR)
-            stage_quad<T, LT, INSIDE, LBL>(J, S, G, gx, gy, 4 * q, grow, s_img + r * P,
-                                       s_lbl + r * P);
+    const int qpr = G.quads, ey = G.e[1];
+    const int nq = G.e[0] * ey * qpr;
+    const float rcp_q = 1.0f / (float)qpr, rcp_y = 1.0f / (float)ey;
+#pragma unroll 2
+    for (int f = threadIdx.x; f < nq; f += kThreads) {
+        const int row = div_small(f, qpr, rcp_q);
+        const int q = f - row * qpr;
+        const int cx = div_small(row, ey, rcp_y);
+        const int cy = row - cx * ey;
+        const int off = row * G.pitch + 4 * q;
+        stage_quad<T, LT, LBL>(J, S, G.lo[0] + cx, G.lo[1] + cy, G.lo[2] + 4 * q, s_img + off,
+                               s_lbl + off);
     }
 }
 
-// Copy the tile's input footprint into LDS in the input type (labels as int8), with
-// fill / label_fill in cells outside the volume.  Each lane moves 4
-// consecutive cells of one row: buffer loads from one VGPR offset (the cell
-// steps are immediates), one 16-byte and one 4-byte LDS store.  When the whole
-// footprint lies inside the volume no per-cell test is compiled in.
 template <typename T, typename LT>
 __device__ __forceinline__ void stage_footprint(const FwdJob &J, const Src &S, const TileGeom &G,
                                                 LT *s_img, int8_t *s_lbl)
 {
-    const bool labels = (J.flags & kFlagLabels) != 0;
-    const bool inside = G.lo[0] >= 0 && G.lo[1] >= 0 && G.lo[2] >= 0 &&
-                        G.lo[0] + G.e[0] <= J.nx && G.lo[1] + G.e[1] <= J.ny &&
-                        G.lo[2] + 4 * G.quads <= J.nz;
-    if (inside) {
-        if (labels)
-            stage_rows<T, LT, true, true>(J, S, G, s_img, s_lbl);
-        else
-            stage_rows<T, LT, true, false>(J, S, G, s_img, s_lbl);
-    } else {
-        if (labels)
-            stage_rows<T, LT, false, true>(J, S, G, s_img, s_lbl);
-        else
-            stage_rows<T, LT, false, false>(J, S, G, s_img, s_lbl);
-    }
+    if (J.flags & kFlagLabels)
+        stage_quads<T, LT, true>(J, S, G, s_img, s_lbl);
+    else
+        stage_quads<T, LT, false>(J, S, G, s_img, s_lbl);
 }
 
 }  // namespace ctaug

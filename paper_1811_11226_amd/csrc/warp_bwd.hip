@@ -46,16 +46,6 @@ int64_t bwd_partial_rows(int64_t ox, int64_t oy, int64_t oz)
     return bwd_grid(bwd_tiles(ox, oy, oz));
 }
 
-// floor(a / b) for 0 <= a < 2^24, 0 < b < 2^16: FP32 reciprocal estimate and
-// one integer correction step.
-__device__ __forceinline__ int div_small(int a, int b, float rcp_b)
-{
-    int q = (int)((float)a * rcp_b);
-    const int r = a - q * b;
-    q += (r >= b) - (r < 0);
-    return q;
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll

@@ -33,7 +33,7 @@ enum : int { kPathOutside, kPathLdsInterior, kPathLdsBoundary, kPathDirectInteri
 
 // All runs of one tile along one sampling path.  Each thread owns runs of 4
 // consecutive output voxels along z.
-template <typename T, typename LT, int PATH, bool ALIGNED>
+template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL>
 __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &SL,
                                          const LT *s_img, const int8_t *s_lbl)
 {
@@ -61,7 +61,8 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
         // mask per flag live across the loop (scalar register pressure).
         uint32_t fl = J.flags;
         asm volatile("" : "+s"(fl));
-        const bool labels = (fl & kFlagLabels) != 0;
+        constexpr bool labels = LBL;      // a template parameter: the 4 voxels of a
+                                          // run stay one basic block
         const bool vec = (fl & kFlagVec) != 0;
         P.flags = fl;
         const int nvalid = ALIGNED ? 4 : min(4, J.oz - z);
@@ -159,27 +160,37 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
 // group and (with 16-byte aligned outputs) one vector store.  LT: type of the
 // LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
 // the LDS reads).
-template <typename T, typename LT, bool ALIGNED>
-__device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, const Tiling &SL,
-                                       uint8_t *s_lds, int32_t lds_cells)
+template <typename T, typename LT, bool ALIGNED, bool LBL>
+__device__ __forceinline__ void fwd_box_l(const FwdJob &J, const TileGeom &G, const Tiling &SL,
+                                         uint8_t *s_lds, int32_t lds_cells)
 {
     LT *s_img = reinterpret_cast<LT *>(s_lds);
     int8_t *s_lbl = reinterpret_cast<int8_t *>(s_lds + lds_label_offset<LT>(lds_cells));
     if (G.cls == kOutside) {
-        run_tile<T, LT, kPathOutside, ALIGNED>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathOutside, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
     } else if (G.lds) {
         stage_footprint<T, LT>(J, make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz), G, s_img, s_lbl);
         __syncthreads();
         if (G.cls == kInterior)
-            run_tile<T, LT, kPathLdsInterior, ALIGNED>(J, G, SL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
         else
-            run_tile<T, LT, kPathLdsBoundary, ALIGNED>(J, G, SL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
         __syncthreads();               // LDS is reused by the next box
     } else if (G.cls == kInterior) {
-        run_tile<T, LT, kPathDirectInterior, ALIGNED>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
     } else {
-        run_tile<T, LT, kPathDirectBoundary, ALIGNED>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
     }
+}
+
+template <typename T, typename LT, bool ALIGNED>
+__device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, const Tiling &SL,
+                                       uint8_t *s_lds, int32_t lds_cells)
+{
+    if (J.flags & kFlagLabels)
+        fwd_box_l<T, LT, ALIGNED, true>(J, G, SL, s_lds, lds_cells);
+    else
+        fwd_box_l<T, LT, ALIGNED, false>(J, G, SL, s_lds, lds_cells);
 }
 
 // One output tile, processed as sub-tiles of the job's sub-tile shape (the
