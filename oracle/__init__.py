@@ -58,11 +58,11 @@ def _declare(L):
     L.orc_box_muller.restype = None
     L.orc_gauss_range.argtypes = [_u64, _u32, _u64, _i64, _p]
     L.orc_gauss_range.restype = None
-    L.orc_photometric.argtypes = [_p, _i64, _p, _int, _u64, _u32, _p]
+    L.orc_photometric.argtypes = [_p, _i64, _p, _int, _u64, _u32, _p, _i64, _p]
     L.orc_photometric.restype = _int
     L.orc_affine_matrix.argtypes = [_p, _p, _p, _p]
     L.orc_affine_matrix.restype = _int
-    L.orc_warp.argtypes = [_p, _p, _p, _p, _p, _int, _p, _dbl, _int, _p, _int, _u64, _u32,
+    L.orc_warp.argtypes = [_p, _p, _p, _p, _p, _int, _p, _dbl, _int, _p, _int, _u64, _u32, _p,
                            _p, _p, _p]
     L.orc_warp.restype = _int
     L.orc_warp_backward.argtypes = [_p, _p, _p, _p, _int, _p, _dbl, _p, _p, _p, _p, _p]
@@ -127,14 +127,22 @@ def _photo6(photo):
     return np.asarray(photo.as_tuple6(), dtype=np.float64)
 
 
+def _occ(photo):
+    pair = photo.occ_pair() if photo is not None else None
+    return None if pair is None else np.asarray(pair, dtype=np.float64)
+
+
 def photometric(vin, photo):
-    """Apply the photometric chain of `photo` (a synth.PhotoParams) to the flat
-    FP64 array `vin`, voxel index = position in the array."""
+    """Apply the occlusion and photometric chain of `photo` (a
+    synth.PhotoParams) to the FP64 array `vin` ([X][Y][Z] or flat), voxel
+    index = position in the array, z = index mod the last axis."""
     v = _c(vin, np.float64).ravel()
     out = np.empty_like(v)
     ph = _photo6(photo)
+    occ = _occ(photo)
+    Z = int(np.shape(vin)[-1]) if np.ndim(vin) else 1
     _check(lib().orc_photometric(_ptr(v), v.size, _ptr(ph), int(bool(photo.window)),
-                                 int(photo.seed), int(photo.volume_id), _ptr(out)))
+                                 int(photo.seed), int(photo.volume_id), _ptr(occ), Z, _ptr(out)))
     return out.reshape(np.shape(vin))
 
 
@@ -170,9 +178,10 @@ def warp(img, M, out_dim, lbl=None, disp=None, fill=-1000.0, label_fill=0, photo
     seed = int(photo.seed) if photo is not None else 0
     vol = int(photo.volume_id) if photo is not None else 0
     window = int(bool(photo.window)) if photo is not None else 0
+    occ = _occ(photo)
     _check(lib().orc_warp(_ptr(img64), _ptr(in_dim), _ptr(lbl8), _ptr(Mf), _ptr(Md), int(exact),
                           _ptr(d), float(fill), int(label_fill), _ptr(ph), window, seed, vol,
-                          _ptr(od), _ptr(out), _ptr(lout)))
+                          _ptr(occ), _ptr(od), _ptr(out), _ptr(lout)))
     return out, lout
 
 

@@ -162,13 +162,32 @@ static double photometric(double V, const double *photo, int window,
     return t == 0.0 ? 0.0 : pow(t, gamma);
 }
 
-int orc_photometric(const double *vin, int64_t n, const double *photo, int window,
-                    uint64_t seed, uint32_t vol, double *out)
+/* ------------------------------------------------------------------------ */
+/* Random occlusion (Sec. GPU-AUG, occlusion paragraph and its I_occ         */
+/* equation).  The occluded region is the slab of output voxels whose third  */
+/* coordinate x_3 (z here) lies in [lo, hi] = [z_start, z_start + delta]; the */
+/* equation's printed inequality cannot hold for delta > 0, and it is read as */
+/* lo <= z <= hi (closed).  Occluded voxels take the value 0 in place of the  */
+/* warped image; noise and window follow as for every voxel, since the noise */
+/* equation adds n to I_occ.  occ = {lo, hi} or NULL (no occlusion).         */
+/* ------------------------------------------------------------------------ */
+
+static int occluded(const double *occ, int64_t z)
 {
-    if (!vin || !out || !photo || n < 0)
+    return occ && (double)z >= occ[0] && (double)z <= occ[1];
+}
+
+/* Photometric chain over a volume whose z extent is Z (the occlusion test
+ * uses z = v mod Z). */
+int orc_photometric(const double *vin, int64_t n, const double *photo, int window,
+                    uint64_t seed, uint32_t vol, const double *occ, int64_t Z, double *out)
+{
+    if (!vin || !out || !photo || n < 0 || (occ && Z <= 0))
         return ORC_EINVAL;
-    for (int64_t v = 0; v < n; ++v)
-        out[v] = photometric(vin[v], photo, window, seed, vol, (uint64_t)v);
+    for (int64_t v = 0; v < n; ++v) {
+        double V = occluded(occ, occ ? v % Z : 0) ? 0.0 : vin[v];
+        out[v] = photometric(V, photo, window, seed, vol, (uint64_t)v);
+    }
     return ORC_OK;
 }
 
@@ -366,7 +385,7 @@ static int dims_ok(const int64_t *d)
 int orc_warp(const double *img, const int64_t *in_dim, const int8_t *lbl,
              const float *Mf, const double *Md, int exact, const float *disp,
              double fill, int label_fill,
-             const double *photo, int window, uint64_t seed, uint32_t vol,
+             const double *photo, int window, uint64_t seed, uint32_t vol, const double *occ,
              const int64_t *out_dim, double *out, int8_t *lbl_out)
 {
     if (!dims_ok(in_dim) || !dims_ok(out_dim))
@@ -386,7 +405,8 @@ int orc_warp(const double *img, const int64_t *in_dim, const int8_t *lbl,
                 float qf[3];
                 coord(&cc, x, y, z, v, q, qf);
                 if (out) {
-                    double V = trilinear(img, in_dim, q, fill, NULL);
+                    /* I_occ: the occluded slab is 0, elsewhere the warped image */
+                    double V = occluded(occ, z) ? 0.0 : trilinear(img, in_dim, q, fill, NULL);
                     out[v] = photo ? photometric(V, photo, window, seed, vol, (uint64_t)v) : V;
                 }
                 if (lbl_out)

@@ -41,6 +41,7 @@ class AugmentRanges:
     win_hi: tuple = (1000.0, 1000.0)
     sigma: tuple = (10.0, 10.0)
     window: bool = True
+    occlusion: float = 0.0                      # delta_max of the occluded slab (0 = none)
 
 
 @dataclass
@@ -54,6 +55,15 @@ class PhotoParams:
     window: bool = False
     seed: int = 0
     volume_id: int = 0
+    occlude: bool = False
+    occ_lo: float = 0.0                         # occluded output slab occ_lo <= z <= occ_hi
+    occ_hi: float = -1.0
+
+    def occ_pair(self):
+        """(occ_lo, occ_hi) rounded to FP32, or None without occlusion."""
+        if not self.occlude:
+            return None
+        return float(np.float32(self.occ_lo)), float(np.float32(self.occ_hi))
 
     def as_tuple6(self):
         """(gain, offset, sigma, win_lo, win_hi, gamma) rounded to FP32, the
@@ -95,9 +105,22 @@ def draw_affine_params(rng, ranges, in_dim, out_dim):
     return p
 
 
-def draw_photo(rng, ranges, seed, volume_id):
-    return PhotoParams(
+def draw_occlusion(rng, delta_max, z_max):
+    """Occluded slab of the output's z axis: height delta ~ U[0, delta_max]
+    and start z ~ U[-delta_max, z_max], so that every z in [0, z_max] has the
+    same chance of being occluded (the paper's occlusion paragraph)."""
+    delta = _u(rng, 0.0, delta_max)
+    start = _u(rng, -delta_max, z_max)
+    return start, start + delta
+
+
+def draw_photo(rng, ranges, seed, volume_id, out_z=None):
+    ph = PhotoParams(
         gain=_u(rng, *ranges.gain), offset=_u(rng, *ranges.offset),
         sigma=_u(rng, *ranges.sigma), win_lo=_u(rng, *ranges.win_lo),
         win_hi=_u(rng, *ranges.win_hi), gamma=_u(rng, *ranges.gamma),
         window=ranges.window, seed=int(seed), volume_id=int(volume_id))
+    if ranges.occlusion > 0 and out_z is not None:
+        ph.occlude = True
+        ph.occ_lo, ph.occ_hi = draw_occlusion(rng, ranges.occlusion, out_z - 1)
+    return ph

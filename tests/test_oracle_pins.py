@@ -621,3 +621,68 @@ def test_fused_photometric_equals_unfused_oracle():
     fused, _ = oracle.warp(img, M, dims, photo=ph)
     plain, _ = oracle.warp(img, M, dims)
     np.testing.assert_array_equal(fused, oracle.photometric(plain, ph))
+
+
+# ---------------------------------------------------------------------------
+# Random occlusion (occlusion paragraph and its I_occ equation)
+# ---------------------------------------------------------------------------
+
+def _occ_case(lo, hi, **kw):
+    rng = np.random.default_rng(31)
+    dims = (10, 9, 14)
+    img, lbl = phantom_pair(dims, seed=71)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    M = oracle.affine_matrix(prm, dims, dims)
+    ph = PhotoParams(occlude=True, occ_lo=lo, occ_hi=hi, **kw)
+    return img, lbl, M, dims, ph
+
+
+@pytest.mark.parametrize("lo,hi,slab", [(3.0, 7.0, [3, 4, 5, 6, 7]), (2.5, 5.5, [3, 4, 5]),
+                                        (-4.0, 0.0, [0]), (12.25, 30.0, [13]),
+                                        (5.2, 5.8, []), (-9.0, -1.0, [])])
+def test_occluded_slab_is_zero_then_photometrics(lo, hi, slab):
+    """Voxels with occ_lo <= z <= occ_hi (closed) take I_occ = 0 before the
+    photometric chain (here gain/offset only: exactly the offset); the rest
+    and every label equal the unoccluded warp."""
+    img, lbl, M, dims, ph = _occ_case(lo, hi, gain=1.5, offset=-12.0, window=False)
+    out, lout = oracle.warp(img, M, dims, lbl=lbl, photo=ph)
+    ref_ph = PhotoParams(gain=1.5, offset=-12.0, window=False)
+    ref, lref = oracle.warp(img, M, dims, lbl=lbl, photo=ref_ph)
+    z = np.arange(dims[2])
+    occ = np.isin(z, slab)
+    assert np.all(out[:, :, occ] == -12.0)
+    np.testing.assert_array_equal(out[:, :, ~occ], ref[:, :, ~occ])
+    np.testing.assert_array_equal(lout, lref)
+
+
+def test_occluded_voxels_still_get_noise_and_window():
+    """The noise equation adds n to I_occ, so occluded voxels are
+    window(offset + sigma n(v)) with the voxel's own Gaussian."""
+    img, lbl, M, dims, ph = _occ_case(4.0, 9.0, gain=1.1, offset=20.0, sigma=25.0, win_lo=-200,
+                                      win_hi=300, gamma=1.0, window=True, seed=7, volume_id=3)
+    out, _ = oracle.warp(img, M, dims, photo=ph)
+    n = oracle.gauss(7, 3, 0, int(np.prod(dims))).reshape(dims)
+    f32 = lambda v: float(np.float32(v))
+    expect = np.clip((f32(20.0) + f32(25.0) * n - f32(-200)) / (f32(300) - f32(-200)), 0, 1)
+    np.testing.assert_allclose(out[:, :, 4:10], expect[:, :, 4:10], rtol=1e-12, atol=1e-15)
+
+
+def test_occlusion_fused_equals_unfused():
+    img, lbl, M, dims, ph = _occ_case(1.0, 6.5, gain=0.95, offset=3.0, sigma=10.0, window=True,
+                                      win_lo=-1000, win_hi=1000, gamma=0.8, seed=5, volume_id=2)
+    fused, _ = oracle.warp(img, M, dims, photo=ph)
+    plain, _ = oracle.warp(img, M, dims)
+    np.testing.assert_array_equal(fused, oracle.photometric(plain, ph))
+
+
+def test_occlusion_draw_covers_every_slice_equally():
+    """Start ~ U[-delta_max, z_max], height ~ U[0, delta_max]: every z in
+    [0, z_max] is occluded with probability (delta_max / 2) / (z_max + delta_max)."""
+    from synth import draw_occlusion
+    rng = np.random.default_rng(2024)
+    dmax, zmax, n = 16.0, 63, 200000
+    draws = np.array([draw_occlusion(rng, dmax, zmax) for _ in range(n)])
+    z = np.arange(zmax + 1)
+    freq = ((draws[:, :1] <= z) & (z <= draws[:, 1:])).mean(0)
+    p = (dmax / 2) / (zmax + dmax)
+    assert np.abs(freq - p).max() < 5 * np.sqrt(p * (1 - p) / n)
