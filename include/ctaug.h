@@ -73,10 +73,15 @@ typedef struct {
 } ctaug_vol;
 
 #define CTAUG_PHOTO_WINDOW 1u   /* apply window [win_lo, win_hi] -> [0,1] and gamma */
+#define CTAUG_PHOTO_OCCLUDE 2u  /* random occlusion of the output slab occ_lo <= z <= occ_hi */
 
 /* Photometric parameters of one volume (Sec. "GPU-accelerated data
- * augmentation", noise and window paragraphs; gain, offset and gamma are
- * additions).  For each output voxel with interpolated value V:
+ * augmentation", occlusion, noise and window paragraphs; gain, offset and
+ * gamma are additions).  For each output voxel p = (x, y, z) with
+ * interpolated value V:
+ *     if OCCLUDE and occ_lo <= z <= occ_hi (FP32 comparisons): V = 0
+ *         (the I_occ equation, its slab read as a closed interval on the
+ *         output's third axis; labels are not occluded)
  *     v = gain * V + offset
  *     v = v + sigma * n(v_index)          n ~ N(0,1), see ctaug_noise
  *     if WINDOW: t = min(max((v - win_lo) / (win_hi - win_lo), 0), 1)
@@ -84,12 +89,14 @@ typedef struct {
  *     else       out = v  (Hounsfield units)
  * Requirements: all values finite; sigma >= 0; gamma > 0; win_hi > win_lo
  * when WINDOW is set.  sigma == 0 adds no noise (the result is exactly the
- * noiseless value). */
+ * noiseless value).  occ_lo / occ_hi are read only with OCCLUDE (an empty
+ * slab, occ_hi < occ_lo, occludes nothing). */
 typedef struct {
     float gain, offset, sigma, win_lo, win_hi, gamma;
     uint32_t flags;        /* CTAUG_PHOTO_* bits */
     uint32_t volume_id;    /* Philox counter word 2 */
     uint64_t seed;         /* Philox key */
+    float occ_lo, occ_hi;  /* occluded output slab (OCCLUDE) */
 } ctaug_photo;
 
 /* Raw draws of the random affine transform (Sec. "GPU-accelerated data
@@ -167,9 +174,10 @@ ctaug_status ctaug_warp_displacement(const ctaug_vol *img_in, const ctaug_vol *l
 /* Photometric transform and noise                                           */
 /* ------------------------------------------------------------------------ */
 
-/* In-place photometric chain (see ctaug_photo) on a F32 volume, voxel index v
- * = linear index in the volume.  Bit-identical to the same chain fused into
- * ctaug_warp_affine.  Errors: EINVAL, EDTYPE (not F32), ESHAPE, EHIP. */
+/* In-place photometric chain (see ctaug_photo, occlusion included) on a F32
+ * volume, voxel index v = linear index in the volume, z = v mod dim[2].
+ * Bit-identical to the same chain fused into ctaug_warp_affine.  Errors:
+ * EINVAL, EDTYPE (not F32), ESHAPE, EHIP. */
 ctaug_status ctaug_photometric_noise(ctaug_vol *inout, const ctaug_photo *photo, void *stream);
 
 /* Noise generator (replaces the per-thread cuRAND generators of the paper's

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "CTAUG_OK", 1: "CTAUG_EINVAL", 2: "CTAUG_EDTYPE", 3: "CTAUG_E
                 4: "CTAUG_EWORKSPACE", 5: "CTAUG_EHIP", 6: "CTAUG_ENODEV"}
 CTAUG_F32, CTAUG_I16, CTAUG_I8 = 0, 1, 2
 CTAUG_PHOTO_WINDOW = 1
+CTAUG_PHOTO_OCCLUDE = 2
 CTAUG_PHOTO_NONE = 0x80000000
 
 
@@ -32,7 +33,7 @@ class Photo(ctypes.Structure):
     _fields_ = [("gain", ctypes.c_float), ("offset", ctypes.c_float), ("sigma", ctypes.c_float),
                 ("win_lo", ctypes.c_float), ("win_hi", ctypes.c_float), ("gamma", ctypes.c_float),
                 ("flags", ctypes.c_uint32), ("volume_id", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("occ_lo", ctypes.c_float), ("occ_hi", ctypes.c_float)]
 
 
 class AffineParams(ctypes.Structure):

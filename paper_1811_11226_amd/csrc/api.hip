@@ -70,7 +70,9 @@ ctaug_status check_photo(const ctaug_photo *p)
     const float vals[6] = {p->gain, p->offset, p->sigma, p->win_lo, p->win_hi, p->gamma};
     if (!finite_all(vals, 6) || p->sigma < 0.0f || !(p->gamma > 0.0f))
         return CTAUG_EINVAL;
-    if (p->flags & ~(uint32_t)CTAUG_PHOTO_WINDOW)
+    if (p->flags & ~(uint32_t)(CTAUG_PHOTO_WINDOW | CTAUG_PHOTO_OCCLUDE))
+        return CTAUG_EINVAL;
+    if ((p->flags & CTAUG_PHOTO_OCCLUDE) && !(std::isfinite(p->occ_lo) && std::isfinite(p->occ_hi)))
         return CTAUG_EINVAL;
     if ((p->flags & CTAUG_PHOTO_WINDOW) && !(p->win_hi > p->win_lo))
         return CTAUG_EINVAL;
@@ -85,6 +87,8 @@ void set_photo(FwdJob &J, const ctaug_photo *p)
     J.win_lo = 0.0f;
     J.inv_range = 1.0f;
     J.gamma = 1.0f;
+    J.occ_lo = 0.0f;
+    J.occ_hi = -1.0f;
     J.vol_id = J.key0 = J.key1 = 0;
     if (!p)
         return;
@@ -104,6 +108,11 @@ void set_photo(FwdJob &J, const ctaug_photo *p)
         J.flags |= kFlagWindow;
         if (p->gamma != 1.0f)
             J.flags |= kFlagGamma;
+    }
+    if (p->flags & CTAUG_PHOTO_OCCLUDE) {
+        J.flags |= kFlagOcclude;
+        J.occ_lo = p->occ_lo;
+        J.occ_hi = p->occ_hi;
     }
 }
 
@@ -350,8 +359,9 @@ extern "C" ctaug_status ctaug_photometric_noise(ctaug_vol *inout, const ctaug_ph
     if (n == 0)
         return CTAUG_OK;
     const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(inout->data) & 15u) == 0;
-    return hip_status(launch_photometric(static_cast<float *>(inout->data), n, photo_from_job(J),
-                                         J.vol_id, J.key0, J.key1, vec, as_stream(stream)));
+    return hip_status(launch_photometric(static_cast<float *>(inout->data), n, inout->dim[2],
+                                         photo_from_job(J), J.occ_lo, J.occ_hi, J.vol_id, J.key0,
+                                         J.key1, vec, as_stream(stream)));
 }
 
 extern "C" ctaug_status ctaug_noise(uint64_t seed, uint32_t volume_id, uint64_t v0, int64_t n,

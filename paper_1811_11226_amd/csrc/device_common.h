@@ -25,6 +25,7 @@ enum : uint32_t {
     kFlagVec = 32u,                    // 16-byte aligned outputs, Zo % 4 == 0
     kFlagFillInT = 64u,                // fill is exactly representable as an int16
     kFlagLds16 = 128u,                 // int16 input staged as int16 LDS cells
+    kFlagOcclude = 256u,               // output z-slab [occ_lo, occ_hi] set to 0
 };
 
 enum : int32_t { kF32 = 0, kI16 = 1, kI8 = 2 };
@@ -47,6 +48,7 @@ struct FwdJob {
     float fill;
     int32_t label_fill;
     float gain, offset, sigma, win_lo, inv_range, gamma;
+    float occ_lo, occ_hi;              // occluded output slab occ_lo <= z <= occ_hi
     uint32_t vol_id, key0, key1;
     int32_t tiles_x, tiles_y, tiles_z; // tile grid of this job's output
     int32_t sub[3];                    // log2 extents of the sub-tiles a tile is staged in

@@ -23,8 +23,9 @@ int32_t lds_cells_cap(int32_t elem_bytes);
 int32_t lds_cells_for(int32_t bound, int32_t elem_bytes);
 size_t lds_bytes_for(int32_t cells, int32_t elem_bytes);
 Tiling choose_subtile(const FwdJob &J, const Tiling &TL, int32_t lds_cells);
-hipError_t launch_photometric(float *data, int64_t n, const Photo &P, uint32_t vol, uint32_t k0,
-                              uint32_t k1, bool vec, hipStream_t s);
+hipError_t launch_photometric(float *data, int64_t n, int64_t nz, const Photo &P, float occ_lo,
+                              float occ_hi, uint32_t vol, uint32_t k0, uint32_t k1, bool vec,
+                              hipStream_t s);
 hipError_t launch_noise(uint64_t v0, int64_t n, uint32_t vol, uint32_t k0, uint32_t k1,
                         float *gauss, uint32_t *words, hipStream_t s);
 

@@ -123,6 +123,16 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
             }
         }
 
+        if (fl & kFlagOcclude) {
+            // I_occ: the occluded output slab is 0 in place of the warped image
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float zf = (float)(z + k);
+                if (zf >= J.occ_lo && zf <= J.occ_hi)
+                    V[k] = 0.0f;
+            }
+        }
+
         if (P.flags & kFlagPhoto) {
             float n[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             if (P.flags & kFlagNoise) {
@@ -430,7 +440,8 @@ hipError_t launch_warp_batch(const FwdJob *jobs_dev, const int32_t *prefix_dev, 
 // Standalone photometric pass (in place) and raw noise generator.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_photometric(float *data, int64_t n, Photo P,
+__global__ __launch_bounds__(kThreads) void k_photometric(float *data, int64_t n, int64_t nz,
+                                                          Photo P, float occ_lo, float occ_hi,
                                                           uint32_t vol, uint32_t k0, uint32_t k1,
                                                           int vec)
 {
@@ -438,33 +449,52 @@ __global__ __launch_bounds__(kThreads) void k_photometric(float *data, int64_t n
     for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < ngroups;
          g += (int64_t)gridDim.x * kThreads) {
         const int64_t v0 = g << 2;
-        float nz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float nzs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (P.flags & kFlagNoise)
-            gauss_group((uint64_t)g, vol, k0, k1, nz);
+            gauss_group((uint64_t)g, vol, k0, k1, nzs);
+        float x[4];
         if (vec) {
-            float4 x = *reinterpret_cast<float4 *>(data + v0);
-            x.x = photometric(P, x.x, nz[0]);
-            x.y = photometric(P, x.y, nz[1]);
-            x.z = photometric(P, x.z, nz[2]);
-            x.w = photometric(P, x.w, nz[3]);
-            *reinterpret_cast<float4 *>(data + v0) = x;
+            const f32x4 w = *reinterpret_cast<const f32x4 *>(data + v0);
+            x[0] = w.x;
+            x[1] = w.y;
+            x[2] = w.z;
+            x[3] = w.w;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                x[k] = v0 + k < n ? data[v0 + k] : 0.0f;
+        }
+        if (P.flags & kFlagOcclude) {
+            const int64_t z0 = v0 % nz;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float zf = (float)((z0 + k) % nz);
+                if (zf >= occ_lo && zf <= occ_hi)
+                    x[k] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            x[k] = photometric(P, x[k], nzs[k]);
+        if (vec) {
+            *reinterpret_cast<f32x4 *>(data + v0) = f32x4{x[0], x[1], x[2], x[3]};
         } else {
             for (int k = 0; k < 4; ++k)
                 if (v0 + k < n)
-                    data[v0 + k] = photometric(P, data[v0 + k], nz[k]);
+                    data[v0 + k] = x[k];
         }
     }
 }
 
-hipError_t launch_photometric(float *data, int64_t n, const Photo &P, uint32_t vol, uint32_t k0,
-                              uint32_t k1, bool vec, hipStream_t s)
+hipError_t launch_photometric(float *data, int64_t n, int64_t nz, const Photo &P, float occ_lo,
+                              float occ_hi, uint32_t vol, uint32_t k0, uint32_t k1, bool vec,
+                              hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
     const int64_t ngroups = (n + 3) >> 2;
     const int64_t blocks = std::min<int64_t>((ngroups + kThreads - 1) / kThreads, 256 * 64);
-    hipLaunchKernelGGL(k_photometric, dim3((unsigned)blocks), dim3(kThreads), 0, s, data, n, P, vol,
-                       k0, k1, vec ? 1 : 0);
+    hipLaunchKernelGGL(k_photometric, dim3((unsigned)blocks), dim3(kThreads), 0, s, data, n, nz, P,
+                       occ_lo, occ_hi, vol, k0, k1, vec ? 1 : 0);
     return hipGetLastError();
 }
 

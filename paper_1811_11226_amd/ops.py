@@ -49,7 +49,8 @@ def _M32(M):
 
 def make_photo(photo):
     """ctypes Photo from any object with gain, offset, sigma, win_lo, win_hi,
-    gamma, window, seed and volume_id attributes (None -> None)."""
+    gamma, window, seed and volume_id attributes, and optionally occlude,
+    occ_lo and occ_hi (None -> None)."""
     if photo is None:
         return None
     p = _lib.Photo()
@@ -58,6 +59,9 @@ def make_photo(photo):
     p.flags = CTAUG_PHOTO_WINDOW if photo.window else 0
     p.volume_id = int(photo.volume_id)
     p.seed = int(photo.seed)
+    if getattr(photo, "occlude", False):
+        p.flags |= _lib.CTAUG_PHOTO_OCCLUDE
+        p.occ_lo, p.occ_hi = float(photo.occ_lo), float(photo.occ_hi)
     return p
 
 

@@ -191,8 +191,9 @@ def test_warp_rejects_bad_arguments(L):
 
 
 @pytest.mark.parametrize("kw", [dict(sigma=-1.0), dict(gamma=0.0), dict(gain=math.nan),
-                                dict(flags=2), dict(flags=1, win_lo=5.0, win_hi=5.0),
-                                dict(offset=math.inf)])
+                                dict(flags=4), dict(flags=1, win_lo=5.0, win_hi=5.0),
+                                dict(offset=math.inf), dict(flags=2, occ_lo=math.nan),
+                                dict(flags=3, occ_hi=math.inf)])
 def test_warp_rejects_bad_photometrics(L, kw):
     ph = photo(**kw)
     assert warp(L, vol((8, 8, 8), I16), None, mat(), 0.0, 0, ph, vol((4, 4, 4)), None) == EINVAL

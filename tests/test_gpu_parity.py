@@ -263,6 +263,47 @@ def test_fused_equals_unfused_bit_exact():
     assert torch.equal(fused, plain)
 
 
+@pytest.mark.parametrize("occ", [(3.0, 11.0), (-5.5, 0.25), (20.5, 20.7), (30.0, 99.0)])
+@pytest.mark.parametrize("dtype,odd", [(np.float32, False), (np.int16, True)])
+def test_occlusion_parity(occ, dtype, odd):
+    """Random occlusion of an output z-slab: labels bit-exact, intensities
+    against the oracle, fused = unfused through photometric_noise."""
+    dims = (40, 36, 37 if odd else 40)
+    job = configs.c1(dims=dims)[0]
+    job.img = job.img.astype(dtype)
+    ph = job.photo
+    ph.occlude, ph.occ_lo, ph.occ_hi = True, occ[0], occ[1]
+    _, out, lout, ref, lref = run_job(job)
+    assert np.array_equal(lout, lref)
+    assert_intensity(out, ref, windowed=True, what=f"occlusion {occ}")
+    _, M = ctaug.affine_matrix(job.prm, job.in_dim, job.out_dim)
+    plain, _ = ctaug.warp_affine(_t(job.img), M, fill=job.fill)
+    ctaug.photometric_noise(plain, ph)
+    fused, _ = ctaug.warp_affine(_t(job.img), M, fill=job.fill, photo=ph)
+    assert torch.equal(fused, plain)
+
+
+def test_occlusion_in_batch_plan():
+    T = _batch_jobs(n=3, out_dim=(36, 30, 44))
+    rng = np.random.default_rng(77)
+    jobs, phs = [], []
+    for (j, M, img, lbl, out, lout) in T:
+        ph = draw_photo(rng, AugmentRanges(occlusion=12.0), seed=9, volume_id=j.volume_id,
+                        out_z=44)
+        phs.append(ph)
+        jobs.append(ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=ph))
+    plan = ctaug.BatchPlan(jobs, tile=(16, 16, 16), lds_cells=8176)
+    plan.launch()
+    for (j, M, img, lbl, out, lout), ph in zip(T, phs):
+        s_out, s_lout = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=ph,
+                                          out_dim=j.out_dim)
+        assert torch.equal(out, s_out) and torch.equal(lout, s_lout)
+        ref, lref = oracle.warp(j.img, M, j.out_dim, lbl=j.lbl, fill=j.fill, photo=ph)
+        assert np.array_equal(_np(lout), lref)
+        assert_intensity(_np(out), ref, windowed=True)
+    plan.close()
+
+
 def test_photometric_noise_parity():
     rng = np.random.default_rng(5)
     v = rng.uniform(-1200, 1500, (30, 17, 11)).astype(np.float32)
