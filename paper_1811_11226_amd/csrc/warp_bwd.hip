@@ -19,6 +19,7 @@
 #include "tile_geom.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace ctaug {
 
@@ -68,6 +69,75 @@ __device__ __forceinline__ void cell_gradient(const float K[8], const float tt[3
                  tt[0]);
 }
 
+// Workgroup-wide min of mn[] and max of mx[] (3 ints each); every thread gets
+// the result.  s_red: 4 x 6 ints of LDS.  Ends with a barrier.
+__device__ __forceinline__ void block_minmax3(int mn[3], int mx[3], int (*s_red)[6])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mn[i] = min(mn[i], __shfl_xor(mn[i], off, 64));
+            mx[i] = max(mx[i], __shfl_xor(mx[i], off, 64));
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            s_red[wave][i] = mn[i];
+            s_red[wave][3 + i] = mx[i];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        mn[i] = s_red[0][i];
+        mx[i] = s_red[0][3 + i];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) {
+            mn[i] = min(mn[i], s_red[w][i]);
+            mx[i] = max(mx[i], s_red[w][3 + i]);
+        }
+    }
+    __syncthreads();
+}
+
+// Footprint of an output box from the range [fmn, fmx] of floor(q) over its
+// guarded samples (fmn > fmx: no guarded sample): cells floor(q) .. floor(q) + 1,
+// clamped to [-1, n].
+__device__ __forceinline__ TileGeom geom_from_cells(const FwdJob &J, int x0, int y0, int z0,
+                                                    int x1, int y1, int z1, const int fmn[3],
+                                                    const int fmx[3], int32_t lds_cells)
+{
+    TileGeom G;
+    G.x0 = x0;
+    G.y0 = y0;
+    G.z0 = z0;
+    G.x1 = x1;
+    G.y1 = y1;
+    G.z1 = z1;
+    G.lds = false;
+    G.quads = 0;
+    G.pitch = 0;
+    if (fmn[0] > fmx[0]) {
+        G.cls = kOutside;
+        return G;
+    }
+    const int n[3] = {J.nx, J.ny, J.nz};
+    bool interior = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int a = max(fmn[i], -1), b = min(fmx[i] + 1, n[i]);
+        G.lo[i] = a;
+        G.e[i] = b - a + 1;
+        interior = interior && a >= 0 && b <= n[i] - 1;
+    }
+    G.quads = (G.e[2] + 3) >> 2;
+    G.pitch = lds_pitch(G.e[2]);
+    G.cls = interior ? kInterior : kBoundary;
+    G.lds = (int64_t)G.e[0] * G.e[1] * G.pitch <= lds_cells;
+    return G;
+}
+
 template <typename T, bool DISP>
 __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__restrict__ g,
                                                        float *__restrict__ g_img,
@@ -91,6 +161,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
 
+    __shared__ int s_red[kThreads / 64][6];
+
     // this thread's run inside every tile
     const int zr = threadIdx.x & 3;
     const int yr = (threadIdx.x >> 2) & 7;
@@ -100,28 +172,23 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         const int tz = t % J.tiles_z, rest = t / J.tiles_z;
         const int ty = rest % J.tiles_y, tx = rest / J.tiles_y;
         const int x0 = tx << TL.lx, y0 = ty << TL.ly, z0 = tz << TL.lz;
-        const TileGeom G = box_geom(J, x0, y0, z0, min(x0 + (1 << TL.lx), J.ox) - 1,
-                                    min(y0 + (1 << TL.ly), J.oy) - 1,
-                                    min(z0 + (1 << TL.lz), J.oz) - 1, lds_cells);
-        const bool lds = G.lds;
-        const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
-        if (lds) {
-            stage_footprint<T, float>(J, src, G, s_cells, nullptr);
-            __syncthreads();
-        }
+        const int x1 = min(x0 + (1 << TL.lx), J.ox) - 1, y1 = min(y0 + (1 << TL.ly), J.oy) - 1,
+                  z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
         const int x = x0 + xr, y = y0 + yr, z = z0 + 4 * zr;
-        // per voxel of the run: LDS cell of corner (0,0,0), fractions, upstream gradient
-        int base[4];
-        float tw[4][3], gk[4];
-        bool live[4] = {false, false, false, false};
-        float S[3] = {0.0f, 0.0f, 0.0f}, Sz[3] = {0.0f, 0.0f, 0.0f};
-        if (x <= G.x1 && y <= G.y1 && z <= G.z1) {
-            const int nvalid = min(4, J.oz - z);
-            const int32_t v0 = (x * J.oy + y) * J.oz + z;
+        const bool run_ok = x <= x1 && y <= y1 && z <= z1;
+        const int nvalid = run_ok ? min(4, J.oz - z) : 0;
+        const int32_t v0 = run_ok ? (x * J.oy + y) * J.oz + z : 0;
+        // coordinates, guard and upstream gradient of the run's voxels
+        float qv[4][3], gpk[4];
+        bool gd[4];
+        {
             float rb[3];
             row_base(J.M, (float)x, (float)y, rb);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                gd[k] = false;
+                gpk[k] = 0.0f;
+                qv[k][0] = qv[k][1] = qv[k][2] = 0.0f;
                 if (k >= nvalid)
                     continue;
                 const int32_t v = v0 + k;
@@ -133,11 +200,56 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                     qy = qy + disp[nvox + v];
                     qz = qz + disp[2 * nvox + v];
                 }
-                const float gp = g[v];
+                qv[k][0] = qx;
+                qv[k][1] = qy;
+                qv[k][2] = qz;
+                gd[k] = !empty_in && in_guard(qx, qy, qz, J.nx, J.ny, J.nz);
+                gpk[k] = g[v];
+            }
+        }
+        TileGeom G;
+        if (DISP) {
+            // no a-priori bound with a displacement field: the footprint is the
+            // range of floor(q) over the tile's guarded samples (block reduction)
+            int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (gd[k])
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const int f = (int)floorf(qv[k][i]);
+                        fmn[i] = min(fmn[i], f);
+                        fmx[i] = max(fmx[i], f);
+                    }
+            block_minmax3(fmn, fmx, s_red);
+            G = geom_from_cells(J, x0, y0, z0, x1, y1, z1, fmn, fmx, lds_cells);
+        } else {
+            G = box_geom(J, x0, y0, z0, x1, y1, z1, lds_cells);
+        }
+        const bool lds = G.lds;
+        const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
+        if (lds) {
+            stage_footprint<T, float>(J, src, G, s_cells, nullptr);
+            __syncthreads();
+        }
+        // per voxel of the run: LDS cell of corner (0,0,0), fractions, upstream gradient
+        int base[4];
+        float tw[4][3], gk[4];
+        bool live[4] = {false, false, false, false};
+        float S[3] = {0.0f, 0.0f, 0.0f}, Sz[3] = {0.0f, 0.0f, 0.0f};
+        if (run_ok) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= nvalid)
+                    continue;
+                const int32_t v = v0 + k;
+                const float zf = (float)(z + k);
+                const float qx = qv[k][0], qy = qv[k][1], qz = qv[k][2];
+                const float gp = gpk[k];
                 float dV[3] = {0.0f, 0.0f, 0.0f};
-                if (!empty_in && in_guard(qx, qy, qz, J.nx, J.ny, J.nz)) {
+                if (gd[k]) {
                     float K[8], tt[3];
-                    if (!DISP && lds) {
+                    if (lds) {
                         const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
                         const int bs = (int)mul24(mul24((uint32_t)((int)fx - G.lo[0]),
                                                         (uint32_t)ey) +
@@ -321,9 +433,10 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
         return hipSuccess;
     }
     const int grid = (int)bwd_grid(ntiles);
-    // LDS cells sized for the largest footprint of any tile (affine warps only)
+    // LDS cells sized for the largest footprint of any tile (a displacement field
+    // has no a-priori bound: the full reservation, used when a tile fits it)
     const int32_t cells =
-        J.disp ? 0 : std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells);
+        J.disp ? kBwdLdsCells : std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells);
     const size_t lds = (size_t)cells * sizeof(float);
     double *part = g_M ? partials : nullptr;
     const bool disp = J.disp != nullptr;

@@ -439,16 +439,21 @@ def test_affine_backward_adjoint_identity_gpu():
     assert abs(lhs - rhs) <= bound
 
 
-def test_displacement_backward_parity():
-    rng = np.random.default_rng(11)
-    dims = (36, 32, 28)
+@pytest.mark.parametrize("amp,dims,dtype", [(2.0, (36, 32, 28), np.float32),
+                                            (60.0, (40, 36, 33), np.int16),
+                                            (0.0, (30, 26, 40), np.float32)])
+def test_displacement_backward_parity(amp, dims, dtype):
+    """Displacement adjoint: tile footprints from the reduced coordinates
+    (small fields: LDS accumulation; a wild field: tiles beyond the LDS
+    reservation take per-corner atomics; zero field = affine)."""
+    rng = np.random.default_rng(11 + int(amp))
     img, _ = phantom_pair(dims, seed=8)
+    img = img.astype(dtype)
     prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
     _, M = ctaug.affine_matrix(prm, dims, dims)
-    disp = rng.uniform(-2, 2, (3,) + dims).astype(np.float32)
+    disp = rng.uniform(-amp, amp, (3,) + dims).astype(np.float32)
     g = rng.standard_normal(dims).astype(np.float32)
-    g_img, g_M, g_disp = ctaug.warp_displacement_backward(_t(img.astype(np.float32)), M, _t(disp),
-                                                          _t(g))
+    g_img, g_M, g_disp = ctaug.warp_displacement_backward(_t(img), M, _t(disp), _t(g))
     r_img, r_M, r_u = oracle.warp_backward(img, M, g, disp=disp, want_u=True)
     assert_grad(_np(g_img), r_img, "g_img")
     assert_grad(_np(g_M), r_M, "g_M")
