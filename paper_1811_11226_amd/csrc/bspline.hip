@@ -2,15 +2,15 @@
 // (gfx950).  Separable evaluation: for an output row (x, y) the x/y weights
 // contract the control grid to a row profile P[comp][gz] once (in LDS), and
 // each voxel then needs only its 4 z-weights and 12 FMAs.  The adjoint runs
-// the same factorisation backwards with fixed-order FP64 reductions, so the
-// control-grid gradient is deterministic.
+// the same factorisation backwards, one axis per pass (z in FP32 per row,
+// then y and x in FP64, each in a fixed order), so the control-grid gradient
+// is deterministic.
 #include "device_common.h"
 #include "launch.h"
 
 namespace ctaug {
 
 constexpr int kRowsPerWG = 4;          // upsample: rows (x, y..y+3) per workgroup
-constexpr int kAdjRows = 64;           // adjoint: rows per workgroup chunk
 constexpr int kMaxG = 64;
 
 struct BsplineGeom {
@@ -113,105 +113,110 @@ __global__ __launch_bounds__(kThreads) void k_bspline_up(const float *__restrict
 // Adjoint, stage 1: for output plane x and a chunk of kAdjRows rows,
 //   R[comp][gy][gz] = sum_{y in chunk} sum_z By_{gy-iy(y)} Bz_{gz-iz(z)} g[comp](x,y,z)
 // written in FP64 to ws[x][chunk][comp][gy][gz].
-__global__ __launch_bounds__(kThreads) void k_bspline_adj_rows(const float *__restrict__ g,
-                                                               BsplineGeom G,
-                                                               double *__restrict__ ws,
-                                                               int32_t nchunks)
+// Adjoint, pass 1 (z): T1[comp][x][y][gz] = sum_z B_{gz - iz(z)}(t(z)) g[comp][x][y][z],
+// one thread per (comp, x, y) row streaming z with 16-byte loads when the
+// rows are aligned.  The z-cell index is nondecreasing along the row, so the
+// four controls a voxel touches slide as a window of four FP32 accumulators;
+// each control's sum is stored once, when the window moves past it.
+__global__ __launch_bounds__(kThreads) void k_bspline_adj_z(const float *__restrict__ g,
+                                                            BsplineGeom G, float *__restrict__ T1,
+                                                            int vec)
 {
-    __shared__ float Q[kAdjRows][3][kMaxG];
-    const int x = blockIdx.x, chunk = blockIdx.y;
-    const int64_t nvox = (int64_t)G.ox * G.oy * G.oz;
-    for (int e = threadIdx.x; e < kAdjRows * 3 * kMaxG; e += kThreads)
-        (&Q[0][0][0])[e] = 0.0f;
-    __syncthreads();
-
-    // Each of the first 3*kAdjRows threads streams one (row, component) along z,
-    // accumulating the four weights of the current z-cell and flushing them to
-    // Q when the cell index (nondecreasing in z) advances.
-    if (threadIdx.x < 3 * kAdjRows) {
-        const int row = threadIdx.x % kAdjRows, comp = threadIdx.x / kAdjRows;
-        const int y = chunk * kAdjRows + row;
-        if (y < G.oy && G.oz > 0) {
-            const float *src = g + comp * nvox + ((int64_t)x * G.oy + y) * G.oz;
-            float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            int32_t cur;
-            float t0;
-            bs_cell(0, G.inv_hz, G.gz, cur, t0);
-            for (int z = 0; z < G.oz; ++z) {
-                int32_t iz;
-                float tz, Bz[4];
-                bs_cell(z, G.inv_hz, G.gz, iz, tz);
-                if (iz != cur) {
-                    for (int c = 0; c < 4; ++c) {
-                        Q[row][comp][cur + c] += a[c];
-                        a[c] = 0.0f;
-                    }
-                    cur = iz;
-                }
-                bs_basis(tz, Bz);
-                const float gv = src[z];
+    const int64_t nrows = 3 * (int64_t)G.ox * G.oy;
+    const int64_t row = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (row >= nrows)
+        return;
+    const float *src = g + row * G.oz;
+    float *dst = T1 + row * G.gz;
+    float w[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int32_t cur = 0;
+    auto add = [&](int z, float v) {
+        int32_t iz;
+        float tz, Bz[4];
+        bs_cell(z, G.inv_hz, G.gz, iz, tz);
+        while (cur < iz) {             // controls below iz are complete
+            dst[cur] = w[0];
+            w[0] = w[1];
+            w[1] = w[2];
+            w[2] = w[3];
+            w[3] = 0.0f;
+            ++cur;
+        }
+        bs_basis(tz, Bz);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    a[c] = __builtin_fmaf(Bz[c], gv, a[c]);
-            }
-            for (int c = 0; c < 4; ++c)
-                Q[row][comp][cur + c] += a[c];
+        for (int c = 0; c < 4; ++c)
+            w[c] = __builtin_fmaf(Bz[c], v, w[c]);
+    };
+    if (vec) {
+        for (int z = 0; z < G.oz; z += 4) {
+            const f32x4 v = *reinterpret_cast<const f32x4 *>(src + z);
+            add(z, v.x);
+            add(z + 1, v.y);
+            add(z + 2, v.z);
+            add(z + 3, v.w);
         }
+    } else {
+        for (int z = 0; z < G.oz; ++z)
+            add(z, src[z]);
     }
-    __syncthreads();
-
-    const int ne = 3 * G.gy * G.gz;
-    double *dst = ws + ((int64_t)x * nchunks + chunk) * ne;
-    for (int e = threadIdx.x; e < ne; e += kThreads) {
-        const int comp = e / (G.gy * G.gz);
-        const int rem = e - comp * G.gy * G.gz;
-        const int gy = rem / G.gz, gz = rem - gy * G.gz;
-        double s = 0.0;
-        for (int row = 0; row < kAdjRows; ++row) {
-            const int y = chunk * kAdjRows + row;
-            if (y >= G.oy)
-                break;
-            int32_t iy;
-            float ty, By[4];
-            bs_cell(y, G.inv_hy, G.gy, iy, ty);
-            const int b = gy - iy;
-            if (b < 0 || b > 3)
-                continue;
-            bs_basis(ty, By);
-            s += (double)By[b] * (double)Q[row][comp][gz];
-        }
-        dst[e] = s;
-    }
+    for (int c = 0; c < 4; ++c)
+        dst[cur + c] = w[c];
+    for (int gz = cur + 4; gz < G.gz; ++gz)
+        dst[gz] = 0.0f;
 }
 
-// Adjoint, stage 2: grad_ctrl[comp][gx][gy][gz] = sum_x Bx_{gx-ix(x)} sum_chunk R.
-__global__ __launch_bounds__(kThreads) void k_bspline_adj_final(const double *__restrict__ ws,
-                                                                BsplineGeom G, int32_t nchunks,
-                                                                float *__restrict__ grad_ctrl)
+// Pass 2 (y): T2[comp][x][gy][gz] = sum_y B_{gy - iy(y)}(t(y)) T1[comp][x][y][gz], FP64,
+// one thread per output, y in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_bspline_adj_y(const float *__restrict__ T1,
+                                                            BsplineGeom G, double *__restrict__ T2)
 {
-    const int ne_plane = 3 * G.gy * G.gz;
-    const int total = G.gx * ne_plane;
-    for (int e = blockIdx.x * kThreads + threadIdx.x; e < total; e += gridDim.x * kThreads) {
-        const int comp = e / (G.gx * G.gy * G.gz);
-        const int rem = e - comp * G.gx * G.gy * G.gz;
-        const int gx = rem / (G.gy * G.gz);
-        const int r2 = rem - gx * G.gy * G.gz;     // gy * Gz + gz
-        double s = 0.0;
-        for (int x = 0; x < G.ox; ++x) {
-            int32_t ix;
-            float tx, Bx[4];
-            bs_cell(x, G.inv_hx, G.gx, ix, tx);
-            const int a = gx - ix;
-            if (a < 0 || a > 3)
-                continue;
-            bs_basis(tx, Bx);
-            double r = 0.0;
-            for (int c = 0; c < nchunks; ++c)
-                r += ws[((int64_t)x * nchunks + c) * ne_plane + comp * G.gy * G.gz + r2];
-            s += (double)Bx[a] * r;
-        }
-        grad_ctrl[e] = (float)s;
+    const int64_t total = 3 * (int64_t)G.ox * G.gy * G.gz;
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= total)
+        return;
+    const int gz = (int)(e % G.gz);
+    const int gy = (int)((e / G.gz) % G.gy);
+    const int64_t cx = e / ((int64_t)G.gz * G.gy);          // comp * ox + x
+    // rows y whose cell reaches control gy: iy in [gy - 3, gy]
+    double s = 0.0;
+    for (int y = 0; y < G.oy; ++y) {
+        int32_t iy;
+        float ty, By[4];
+        bs_cell(y, G.inv_hy, G.gy, iy, ty);
+        const int b = gy - iy;
+        if (b < 0 || b > 3)
+            continue;
+        bs_basis(ty, By);
+        s += (double)By[b] * (double)T1[(cx * G.oy + y) * G.gz + gz];
     }
+    T2[e] = s;
+}
+
+// Pass 3 (x): grad_ctrl[comp][gx][gy][gz] = sum_x B_{gx - ix(x)}(t(x)) T2[comp][x][gy][gz].
+__global__ __launch_bounds__(kThreads) void k_bspline_adj_x(const double *__restrict__ T2,
+                                                            BsplineGeom G,
+                                                            float *__restrict__ grad_ctrl)
+{
+    const int total = 3 * G.gx * G.gy * G.gz;
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= total)
+        return;
+    const int plane = G.gy * G.gz;
+    const int comp = e / (G.gx * plane);
+    const int rem = e - comp * G.gx * plane;
+    const int gx = rem / plane, r2 = rem - gx * plane;
+    double s = 0.0;
+    for (int x = 0; x < G.ox; ++x) {
+        int32_t ix;
+        float tx, Bx[4];
+        bs_cell(x, G.inv_hx, G.gx, ix, tx);
+        const int a = gx - ix;
+        if (a < 0 || a > 3)
+            continue;
+        bs_basis(tx, Bx);
+        s += (double)Bx[a] * T2[((int64_t)comp * G.ox + x) * plane + r2];
+    }
+    grad_ctrl[e] = (float)s;
 }
 
 static BsplineGeom geom(const int64_t G[3], const int64_t od[3])
@@ -231,10 +236,16 @@ static BsplineGeom geom(const int64_t G[3], const int64_t od[3])
 
 int bspline_max_grid() { return kMaxG; }
 
+// Workspace of the adjoint: T1 (FP32, 3 x ox x oy x Gz), then T2 (FP64,
+// 3 x ox x Gy x Gz) at a 256-byte aligned offset.
+static int64_t adj_t1_bytes(const int64_t od[3], const int64_t G[3])
+{
+    return ((3 * od[0] * od[1] * G[2] * (int64_t)sizeof(float)) + 255) & ~(int64_t)255;
+}
+
 int64_t bspline_adj_ws_bytes(const int64_t od[3], const int64_t G[3])
 {
-    const int64_t nchunks = (od[1] + kAdjRows - 1) / kAdjRows;
-    return od[0] * nchunks * 3 * G[1] * G[2] * (int64_t)sizeof(double);
+    return adj_t1_bytes(od, G) + 3 * od[0] * G[1] * G[2] * (int64_t)sizeof(double);
 }
 
 hipError_t launch_bspline_up(const float *ctrl, const int64_t G[3], const int64_t od[3],
@@ -251,21 +262,29 @@ hipError_t launch_bspline_up(const float *ctrl, const int64_t G[3], const int64_
 hipError_t launch_bspline_adj(const float *grad_disp, const int64_t od[3], const int64_t G[3],
                               float *grad_ctrl, double *ws, hipStream_t s)
 {
-    const BsplineGeom g = geom(G, od);
-    const int32_t nchunks = (int32_t)((od[1] + kAdjRows - 1) / kAdjRows);
-    if (od[0] > 0 && od[1] > 0 && od[2] > 0) {
-        hipLaunchKernelGGL(k_bspline_adj_rows, dim3((unsigned)od[0], (unsigned)nchunks),
-                           dim3(kThreads), 0, s, grad_disp, g, ws, nchunks);
+    BsplineGeom g = geom(G, od);
+    if (od[0] == 0 || od[1] == 0 || od[2] == 0)
+        g.ox = 0;                      // no voxels: every control gradient is 0
+    float *T1 = reinterpret_cast<float *>(ws);
+    double *T2 = reinterpret_cast<double *>(reinterpret_cast<char *>(ws) + adj_t1_bytes(od, G));
+    if (g.ox > 0) {
+        const int64_t rows = 3 * od[0] * od[1];
+        const bool vec = od[2] % 4 == 0 && (reinterpret_cast<uintptr_t>(grad_disp) & 15u) == 0;
+        hipLaunchKernelGGL(k_bspline_adj_z, dim3((unsigned)((rows + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, s, grad_disp, g, T1, vec ? 1 : 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
+        const int64_t n2 = 3 * od[0] * G[1] * G[2];
+        hipLaunchKernelGGL(k_bspline_adj_y, dim3((unsigned)((n2 + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, s, T1, g, T2);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    BsplineGeom gf = g;
-    if (od[1] == 0 || od[2] == 0)
-        gf.ox = 0;                      // no voxels: every control gradient is 0
     const int total = (int)(3 * G[0] * G[1] * G[2]);
-    hipLaunchKernelGGL(k_bspline_adj_final, dim3((unsigned)((total + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, s, ws, gf, nchunks, grad_ctrl);
+    hipLaunchKernelGGL(k_bspline_adj_x, dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, T2, g, grad_ctrl);
     return hipGetLastError();
 }
 
