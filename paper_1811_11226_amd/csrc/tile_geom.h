@@ -11,6 +11,8 @@
 
 #include "device_common.h"
 
+#include <climits>
+
 namespace ctaug {
 
 enum : int { kOutside = 0, kInterior = 1, kBoundary = 2 };
@@ -210,6 +212,74 @@ __device__ __forceinline__ void stage_footprint(const FwdJob &J, const Src &S, c
         stage_quads<T, LT, true>(J, S, G, s_img, s_lbl);
     else
         stage_quads<T, LT, false>(J, S, G, s_img, s_lbl);
+}
+
+// Workgroup-wide min of mn[] and max of mx[] (3 ints each); every thread gets
+// the result.  s_red: 4 x 6 ints of LDS.  Ends with a barrier.
+__device__ __forceinline__ void block_minmax3(int mn[3], int mx[3], int (*s_red)[6])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mn[i] = min(mn[i], __shfl_xor(mn[i], off, 64));
+            mx[i] = max(mx[i], __shfl_xor(mx[i], off, 64));
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            s_red[wave][i] = mn[i];
+            s_red[wave][3 + i] = mx[i];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        mn[i] = s_red[0][i];
+        mx[i] = s_red[0][3 + i];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) {
+            mn[i] = min(mn[i], s_red[w][i]);
+            mx[i] = max(mx[i], s_red[w][3 + i]);
+        }
+    }
+    __syncthreads();
+}
+
+// Footprint of an output box from the range [fmn, fmx] of floor(q) over its
+// guarded samples (fmn > fmx: no guarded sample): cells floor(q) .. floor(q) + 1,
+// clamped to [-1, n].
+__device__ __forceinline__ TileGeom geom_from_cells(const FwdJob &J, int x0, int y0, int z0,
+                                                    int x1, int y1, int z1, const int fmn[3],
+                                                    const int fmx[3], int32_t lds_cells)
+{
+    TileGeom G;
+    G.x0 = x0;
+    G.y0 = y0;
+    G.z0 = z0;
+    G.x1 = x1;
+    G.y1 = y1;
+    G.z1 = z1;
+    G.lds = false;
+    G.quads = 0;
+    G.pitch = 0;
+    if (fmn[0] > fmx[0]) {
+        G.cls = kOutside;
+        return G;
+    }
+    const int n[3] = {J.nx, J.ny, J.nz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int a = max(fmn[i], -1), b = min(fmx[i] + 1, n[i]);
+        G.lo[i] = a;
+        G.e[i] = b - a + 1;
+    }
+    G.quads = (G.e[2] + 3) >> 2;
+    G.pitch = lds_pitch(G.e[2]);
+    // samples outside the guard may remain: always the per-sample checked path
+    G.cls = kBoundary;
+    G.lds = (int64_t)G.e[0] * G.e[1] * G.pitch <= lds_cells;
+    return G;
 }
 
 }  // namespace ctaug

@@ -33,7 +33,7 @@ enum : int { kPathOutside, kPathLdsInterior, kPathLdsBoundary, kPathDirectInteri
 
 // All runs of one tile along one sampling path.  Each thread owns runs of 4
 // consecutive output voxels along z.
-template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL>
+template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL, bool DISP>
 __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &SL,
                                          const LT *s_img, const int8_t *s_lbl)
 {
@@ -81,6 +81,11 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
             const float zf = (float)(z + k);
             float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
                   qz = coord(J.M, 2, rb, zf);
+            if (DISP) {
+                qx = qx + disp[v0 + k];
+                qy = qy + disp[nvox + v0 + k];
+                qz = qz + disp[2 * nvox + v0 + k];
+            }
             if (PATH == kPathLdsInterior || PATH == kPathLdsBoundary) {
                 if (PATH == kPathLdsBoundary && !in_guard(qx, qy, qz, J.nx, J.ny, J.nz))
                     continue;
@@ -106,11 +111,6 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                                        (uint32_t)pitch) + jz];
                 }
             } else {
-                if (J.disp) {
-                    qx = qx + disp[v0 + k];
-                    qy = qy + disp[nvox + v0 + k];
-                    qz = qz + disp[2 * nvox + v0 + k];
-                }
                 if (PATH == kPathDirectInterior) {
                     V[k] = sample_interior<T>(S, qx, qy, qz);
                     if (labels)
@@ -170,37 +170,37 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
 // group and (with 16-byte aligned outputs) one vector store.  LT: type of the
 // LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
 // the LDS reads).
-template <typename T, typename LT, bool ALIGNED, bool LBL>
+template <typename T, typename LT, bool ALIGNED, bool LBL, bool DISP>
 __device__ __forceinline__ void fwd_box_l(const FwdJob &J, const TileGeom &G, const Tiling &SL,
                                          uint8_t *s_lds, int32_t lds_cells)
 {
     LT *s_img = reinterpret_cast<LT *>(s_lds);
     int8_t *s_lbl = reinterpret_cast<int8_t *>(s_lds + lds_label_offset<LT>(lds_cells));
     if (G.cls == kOutside) {
-        run_tile<T, LT, kPathOutside, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathOutside, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
     } else if (G.lds) {
         stage_footprint<T, LT>(J, make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz), G, s_img, s_lbl);
         __syncthreads();
         if (G.cls == kInterior)
-            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
         else
-            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
         __syncthreads();               // LDS is reused by the next box
     } else if (G.cls == kInterior) {
-        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
     } else {
-        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
     }
 }
 
-template <typename T, typename LT, bool ALIGNED>
+template <typename T, typename LT, bool ALIGNED, bool DISP>
 __device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, const Tiling &SL,
                                        uint8_t *s_lds, int32_t lds_cells)
 {
     if (J.flags & kFlagLabels)
-        fwd_box_l<T, LT, ALIGNED, true>(J, G, SL, s_lds, lds_cells);
+        fwd_box_l<T, LT, ALIGNED, true, DISP>(J, G, SL, s_lds, lds_cells);
     else
-        fwd_box_l<T, LT, ALIGNED, false>(J, G, SL, s_lds, lds_cells);
+        fwd_box_l<T, LT, ALIGNED, false, DISP>(J, G, SL, s_lds, lds_cells);
 }
 
 // One output tile, processed as sub-tiles of the job's sub-tile shape (the
@@ -209,7 +209,7 @@ __device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, cons
 // group and (with 16-byte aligned outputs) one vector store.  LT: type of the
 // LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
 // the LDS reads).
-template <typename T, typename LT, bool ALIGNED>
+template <typename T, typename LT, bool ALIGNED, bool DISP>
 __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling &TL,
                                             int32_t lds_cells, uint8_t *s_lds)
 {
@@ -222,24 +222,61 @@ __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling
     const int y1 = min(y0 + (1 << TL.ly), J.oy) - 1;
     const int z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
     const Tiling SL = {J.sub[0], J.sub[1], J.sub[2]};
+    if (DISP) {
+        // A displacement field has no a-priori footprint bound: the tile (one
+        // run of 4 z voxels per thread) reduces floor(q) over its guarded
+        // samples, and stages that footprint when it fits the reservation.
+        __shared__ int s_red[kThreads / 64][6];
+        const int zr = threadIdx.x & ((1 << (TL.lz - 2)) - 1);
+        const int rr = threadIdx.x >> (TL.lz - 2);
+        const int x = x0 + (rr >> TL.ly), y = y0 + (rr & ((1 << TL.ly) - 1)), z = z0 + 4 * zr;
+        int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
+        if (x <= x1 && y <= y1 && z <= z1 && J.nx > 0 && J.ny > 0 && J.nz > 0) {
+            gconst<float> *disp = gc<float>(J.disp);
+            const int32_t nvox = J.ox * J.oy * J.oz;
+            const int32_t v0 = (x * J.oy + y) * J.oz + z;
+            float rb[3];
+            row_base(J.M, (float)x, (float)y, rb);
+            for (int k = 0; k < min(4, J.oz - z); ++k) {
+                const float zf = (float)(z + k);
+                const float q[3] = {coord(J.M, 0, rb, zf) + disp[v0 + k],
+                                    coord(J.M, 1, rb, zf) + disp[nvox + v0 + k],
+                                    coord(J.M, 2, rb, zf) + disp[2 * nvox + v0 + k]};
+                if (!in_guard(q[0], q[1], q[2], J.nx, J.ny, J.nz))
+                    continue;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int f = (int)floorf(q[i]);
+                    fmn[i] = min(fmn[i], f);
+                    fmx[i] = max(fmx[i], f);
+                }
+            }
+        }
+        block_minmax3(fmn, fmx, s_red);
+        TileGeom G = geom_from_cells(J, x0, y0, z0, x1, y1, z1, fmn, fmx, lds_cells);
+        if (G.lds && (J.flags & kFlagLds16) && !(J.flags & kFlagFillInT))
+            G.lds = false;             // an int16 footprint must hold fill exactly
+        fwd_box<T, LT, ALIGNED, true>(J, G, TL, s_lds, lds_cells);
+        return;
+    }
     for (int sx = x0; sx <= x1; sx += 1 << SL.lx)
         for (int sy = y0; sy <= y1; sy += 1 << SL.ly)
             for (int sz = z0; sz <= z1; sz += 1 << SL.lz) {
                 const TileGeom G = box_geom(J, sx, sy, sz, min(sx + (1 << SL.lx) - 1, x1),
                                             min(sy + (1 << SL.ly) - 1, y1),
                                             min(sz + (1 << SL.lz) - 1, z1), lds_cells);
-                fwd_box<T, LT, ALIGNED>(J, G, SL, s_lds, lds_cells);
+                fwd_box<T, LT, ALIGNED, false>(J, G, SL, s_lds, lds_cells);
             }
 }
 
-template <typename T, bool ALIGNED>
+template <typename T, bool ALIGNED, bool DISP>
 __device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &TL,
                                          int32_t lds_cells, uint8_t *s_lds)
 {
     if (sizeof(T) == 2 && (J.flags & kFlagLds16))
-        fwd_tile_lt<T, T, ALIGNED>(J, t, TL, lds_cells, s_lds);
+        fwd_tile_lt<T, T, ALIGNED, DISP>(J, t, TL, lds_cells, s_lds);
     else
-        fwd_tile_lt<T, float, ALIGNED>(J, t, TL, lds_cells, s_lds);
+        fwd_tile_lt<T, float, ALIGNED, DISP>(J, t, TL, lds_cells, s_lds);
 }
 
 // Dynamic LDS: lds_cells input-type cells of image footprint (rounded up to
@@ -247,7 +284,7 @@ __device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &T
 extern __shared__ __attribute__((aligned(16))) uint8_t s_footprint[];
 
 // Single job, job in kernel arguments, one workgroup per tile.
-template <typename T, bool ALIGNED>
+template <typename T, bool ALIGNED, bool DISP>
 __global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, int32_t ntiles,
                                                           int32_t lds_cells)
 {
@@ -256,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, i
     const int t = (b & 7) * per + (b >> 3);
     if (t >= ntiles)
         return;
-    fwd_tile<T, ALIGNED>(J, t, TL, lds_cells, s_footprint);
+    fwd_tile<T, ALIGNED, DISP>(J, t, TL, lds_cells, s_footprint);
 }
 
 // Batch of jobs from a device table.  prefix[j] = first global tile of job j,
@@ -284,15 +321,15 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
         const FwdJob J = jobs[j];
         const int lt = t - prefix[j];
         if (MODE == kBatchI16F32)
-            fwd_tile_lt<int16_t, float, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile_lt<int16_t, float, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
         else if (MODE == kBatchI16I16)
-            fwd_tile_lt<int16_t, int16_t, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile_lt<int16_t, int16_t, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
         else if (MODE == kBatchF32)
-            fwd_tile_lt<float, float, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile_lt<float, float, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
         else if (J.dtype == kI16)
-            fwd_tile<int16_t, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile<int16_t, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
         else
-            fwd_tile<float, ALIGNED>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile<float, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
     }
 }
 
@@ -364,36 +401,58 @@ size_t lds_bytes_for(int32_t cells, int32_t elem_bytes)
     return (((size_t)cells * (size_t)elem_bytes + 15) & ~(size_t)15) + (size_t)cells;
 }
 
-hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s)
+template <bool DISP>
+static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32_t cells, int grid,
+                            size_t lds, bool aligned, hipStream_t s)
 {
+    if (J.dtype == kI16) {
+        if (aligned)
+            hipLaunchKernelGGL((k_warp_single<int16_t, true, DISP>), dim3(grid), dim3(kThreads), lds,
+                               s, J, TL, ntiles, cells);
+        else
+            hipLaunchKernelGGL((k_warp_single<int16_t, false, DISP>), dim3(grid), dim3(kThreads),
+                               lds, s, J, TL, ntiles, cells);
+    } else {
+        if (aligned)
+            hipLaunchKernelGGL((k_warp_single<float, true, DISP>), dim3(grid), dim3(kThreads), lds,
+                               s, J, TL, ntiles, cells);
+        else
+            hipLaunchKernelGGL((k_warp_single<float, false, DISP>), dim3(grid), dim3(kThreads), lds,
+                               s, J, TL, ntiles, cells);
+    }
+}
+
+// Displacement warps: 8 x 8 x 16 tiles (one run of 4 z voxels per thread, so
+// that a tile can reduce its coordinate range before staging) and a fixed
+// reservation, since the footprint has no a-priori bound.
+constexpr Tiling kDispTiling = {3, 3, 4};
+constexpr int32_t kDispLdsCells = 10224;
+
+hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s)
+{
+    FwdJob Js = J0;
+    const Tiling TL = J0.disp ? kDispTiling : TL0;
+    Js.tiles_x = (Js.ox + (1 << TL.lx) - 1) >> TL.lx;
+    Js.tiles_y = (Js.oy + (1 << TL.ly) - 1) >> TL.ly;
+    Js.tiles_z = (Js.oz + (1 << TL.lz) - 1) >> TL.lz;
+    const FwdJob &J = Js;
     const int ntiles = J.tiles_x * J.tiles_y * J.tiles_z;
     if (ntiles == 0)
         return hipSuccess;
     const int grid = ((ntiles + 7) >> 3) << 3;
     const int32_t esz = (J.flags & kFlagLds16) ? 2 : 4;
-    const int32_t cells = J.disp ? 0 : lds_cells_for(footprint_cells_bound(J, TL), esz);
+    const int32_t cells = J.disp ? lds_cells_for(kDispLdsCells, esz)
+                                 : lds_cells_for(footprint_cells_bound(J, TL), esz);
     const size_t lds = lds_bytes_for(cells, esz);
     const bool aligned = J.oz % 4 == 0;
-    FwdJob Js = J;
     const Tiling SL = choose_subtile(J, TL, cells);
     Js.sub[0] = SL.lx;
     Js.sub[1] = SL.ly;
     Js.sub[2] = SL.lz;
-    if (J.dtype == kI16) {
-        if (aligned)
-            hipLaunchKernelGGL((k_warp_single<int16_t, true>), dim3(grid), dim3(kThreads), lds, s,
-                               Js, TL, ntiles, cells);
-        else
-            hipLaunchKernelGGL((k_warp_single<int16_t, false>), dim3(grid), dim3(kThreads), lds, s,
-                               Js, TL, ntiles, cells);
-    } else {
-        if (aligned)
-            hipLaunchKernelGGL((k_warp_single<float, true>), dim3(grid), dim3(kThreads), lds, s, Js,
-                               TL, ntiles, cells);
-        else
-            hipLaunchKernelGGL((k_warp_single<float, false>), dim3(grid), dim3(kThreads), lds, s, Js,
-                               TL, ntiles, cells);
-    }
+    if (J.disp)
+        launch_single_t<true>(Js, TL, ntiles, cells, grid, lds, aligned, s);
+    else
+        launch_single_t<false>(Js, TL, ntiles, cells, grid, lds, aligned, s);
     return hipGetLastError();
 }
 

@@ -297,8 +297,16 @@ class BatchPlan:
         self._h = h
         self.n = len(jobs)
 
+    @staticmethod
+    def job_array(jobs):
+        """The ctypes array of a list of jobs, reusable across update() calls."""
+        return (_lib.Job * len(jobs))(*jobs)
+
     def update(self, jobs):
-        arr = (_lib.Job * len(jobs))(*jobs)
+        """New job contents: a list of jobs or an array from job_array()."""
+        arr = jobs if isinstance(jobs, ctypes.Array) else self.job_array(jobs)
+        if len(arr) != self.n:
+            raise ValueError(f"expected {self.n} jobs, got {len(arr)}")
         _lib.check(self._L.ctaug_batch_plan_update(self._h, arr), "ctaug_batch_plan_update")
 
     def launch(self):

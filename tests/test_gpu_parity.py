@@ -328,15 +328,21 @@ def test_repeat_runs_bit_identical():
 # Displacement warp and B-spline field
 # ---------------------------------------------------------------------------
 
-def test_displacement_warp_parity_given_field():
-    rng = np.random.default_rng(6)
-    in_dim, out_dim = (40, 36, 28), (38, 34, 24)
+@pytest.mark.parametrize("amp,out_dim,dtype", [(3.0, (38, 34, 24), np.float32),
+                                               (80.0, (30, 26, 21), np.int16),
+                                               (0.4, (45, 40, 37), np.int16)])
+def test_displacement_warp_parity_given_field(amp, out_dim, dtype):
+    """Displacement warps: per-tile footprints from the reduced coordinates
+    (LDS staging), and a wild field whose tiles exceed the reservation
+    (direct gathers)."""
+    rng = np.random.default_rng(6 + int(amp))
+    in_dim = (40, 36, 28)
     img, lbl = phantom_pair(in_dim, seed=77)
     prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
     _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
-    disp = rng.uniform(-3, 3, (3,) + out_dim).astype(np.float32)
+    disp = rng.uniform(-amp, amp, (3,) + out_dim).astype(np.float32)
     ph = draw_photo(rng, AugmentRanges(), seed=99, volume_id=1)
-    out, lout = ctaug.warp_displacement(_t(img.astype(np.float32)), M, _t(disp), lbl=_t(lbl),
+    out, lout = ctaug.warp_displacement(_t(img.astype(dtype)), M, _t(disp), lbl=_t(lbl),
                                         photo=ph)
     ref, lref = oracle.warp(img, M, out_dim, lbl=lbl, disp=disp, photo=ph)
     assert np.array_equal(_np(lout), lref)
