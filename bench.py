@@ -67,7 +67,7 @@ def source_hash():
     """Hash of the sources the batched forward kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1811_11226_amd", "csrc")
-    for name in ("device_common.h", "warp_fwd.hip"):
+    for name in ("device_common.h", "tile_geom.h", "warp_fwd.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())

@@ -25,7 +25,7 @@ def _t(a):
 
 def _np(t):
     torch.cuda.synchronize()
-    return t.cpu().numpy()
+    return t.detach().cpu().numpy()
 
 
 def assert_intensity(got, ref, windowed, what=""):
@@ -464,6 +464,38 @@ def test_displacement_backward_parity(amp, dims, dtype):
     assert_grad(_np(g_img), r_img, "g_img")
     assert_grad(_np(g_M), r_M, "g_M")
     assert_grad(_np(g_disp), r_u, "g_disp")
+
+
+def test_autograd_affine_and_nonrigid_chain():
+    """torch.autograd through the library's adjoints: image and M gradients of
+    the affine warp, and the control-grid gradient through B-spline
+    upsampling and the displacement warp, against the oracle."""
+    from paper_1811_11226_amd import autograd as ag
+    rng = np.random.default_rng(33)
+    dims = (24, 20, 28)
+    img_np, _ = phantom_pair(dims, seed=4)
+    img_np = img_np.astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M32 = ctaug.affine_matrix(prm, dims, dims)
+    g = rng.standard_normal(dims).astype(np.float32)
+
+    img = _t(img_np).requires_grad_(True)
+    M = torch.tensor(M32.astype(np.float64), requires_grad=True)      # host, FP64
+    out = ag.warp_affine(img, M, fill=-1000.0)
+    (out * _t(g)).sum().backward()
+    r_img, r_M, _ = oracle.warp_backward(img_np, M32, g)
+    assert_grad(_np(img.grad), r_img, "autograd g_img")
+    assert M.grad.dtype == torch.float64 and M.grad.device.type == "cpu"
+    assert_grad(M.grad.numpy(), r_M, "autograd g_M")
+
+    ctrl = rng.normal(0.0, 2.0, (3, 6, 6, 6)).astype(np.float32)
+    c = _t(ctrl).requires_grad_(True)
+    u = ag.bspline_upsample(c, dims)
+    out2 = ag.warp_displacement(_t(img_np), torch.tensor(M32.astype(np.float64)), u)
+    (out2 * _t(g)).sum().backward()
+    _, _, r_u = oracle.warp_backward(img_np, M32, g, disp=_np(u), want_img=False, want_M=False,
+                                     want_u=True)
+    assert_grad(_np(c.grad), oracle.bspline_adjoint(r_u, (6, 6, 6)), "autograd g_ctrl")
 
 
 # ---------------------------------------------------------------------------
