@@ -71,6 +71,10 @@ def _declare(L):
     L.orc_bspline_upsample.restype = _int
     L.orc_bspline_adjoint.argtypes = [_p, _p, _p, _p]
     L.orc_bspline_adjoint.restype = _int
+    L.orc_resample_sigma.argtypes = [_p, _dbl, _p]
+    L.orc_resample_sigma.restype = None
+    L.orc_gaussian_smooth.argtypes = [_p, _p, _p, _p]
+    L.orc_gaussian_smooth.restype = _int
 
 
 def _ptr(a):
@@ -222,4 +226,25 @@ def bspline_adjoint(g_u, grid):
     G = _dims(grid)
     out = np.empty((3,) + tuple(G), dtype=np.float64)
     _check(lib().orc_bspline_adjoint(_ptr(g), _ptr(od), _ptr(G), _ptr(out)))
+    return out
+
+
+# -- resampling pre-step ----------------------------------------------------
+
+def resample_sigma(spacing, target):
+    """Smoothing sigma per axis (input voxels) before resampling a volume of
+    voxel spacing `spacing` to `target`."""
+    sp = _c(spacing, np.float64)
+    out = np.zeros(3, dtype=np.float64)
+    lib().orc_resample_sigma(_ptr(sp), float(target), _ptr(out))
+    return out
+
+
+def gaussian_smooth(img, sigma):
+    """Separable Gaussian smoothing (FP64) of a [X][Y][Z] volume."""
+    v = _c(img, np.float64)
+    d = _dims(v.shape)
+    sg = _c(sigma, np.float64)
+    out = np.empty_like(v)
+    _check(lib().orc_gaussian_smooth(_ptr(v), _ptr(d), _ptr(sg), _ptr(out)))
     return out

@@ -579,3 +579,91 @@ int orc_bspline_adjoint(const double *g_u, const int64_t *out_dim, const int64_t
             }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Resampling pre-step (Sec. "Pre- and post-processing"): before a volume of */
+/* voxel spacing u_k is resampled to spacing r, it is smoothed by a Gaussian */
+/* g(x) proportional to exp(-sum_k x_k^2 / sigma_k^2) with                    */
+/* sigma_k = max(r / u_k - 1, 0) / 3 (in input voxels).  The kernel as        */
+/* printed has no factor 2 in the exponent, so its standard deviation per     */
+/* axis is sigma_k / sqrt(2).  Readings: the separable kernel is sampled at  */
+/* integer offsets |d| <= R_k = floor(3 sigma_k / sqrt(2) + 0.5) (three       */
+/* standard deviations) and normalised to sum 1; voxels beyond the volume    */
+/* repeat the nearest edge voxel; sigma_k = 0 leaves axis k unchanged.        */
+/* ------------------------------------------------------------------------ */
+
+void orc_resample_sigma(const double *spacing, double target, double *sigma)
+{
+    for (int k = 0; k < 3; ++k) {
+        double s = (target / spacing[k] - 1.0) / 3.0;
+        sigma[k] = s > 0.0 ? s : 0.0;
+    }
+}
+
+static int64_t gauss_radius(double sigma)
+{
+    return sigma > 0.0 ? (int64_t)floor(3.0 * sigma / sqrt(2.0) + 0.5) : 0;
+}
+
+/* One axis of the separable smoothing, in place through a scratch line. */
+static void smooth_axis(double *vol, const int64_t *dim, int axis, double sigma)
+{
+    const int64_t R = gauss_radius(sigma);
+    if (R == 0)
+        return;
+    double *w = malloc(sizeof(double) * (size_t)(R + 1));
+    double sum = 0.0;
+    for (int64_t d = 0; d <= R; ++d) {
+        w[d] = exp(-(double)(d * d) / (sigma * sigma));
+        sum += d == 0 ? w[d] : 2.0 * w[d];
+    }
+    for (int64_t d = 0; d <= R; ++d)
+        w[d] /= sum;
+    const int64_t n = dim[axis];
+    const int64_t stride = axis == 0 ? dim[1] * dim[2] : axis == 1 ? dim[2] : 1;
+    const int64_t lines = dim[0] * dim[1] * dim[2] / n;
+#pragma omp parallel
+    {
+        double *line = malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t l = 0; l < lines; ++l) {
+            /* base of line l: the other two coordinates in C order */
+            int64_t base;
+            if (axis == 2)
+                base = l * n;
+            else if (axis == 1)
+                base = (l / dim[2]) * dim[1] * dim[2] + (l % dim[2]);
+            else
+                base = l;
+            for (int64_t i = 0; i < n; ++i)
+                line[i] = vol[base + i * stride];
+            for (int64_t i = 0; i < n; ++i) {
+                double acc = 0.0;
+                for (int64_t d = -R; d <= R; ++d) {
+                    int64_t j = i + d;
+                    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+                    acc += w[d < 0 ? -d : d] * line[j];
+                }
+                vol[base + i * stride] = acc;
+            }
+        }
+        free(line);
+    }
+    free(w);
+}
+
+int orc_gaussian_smooth(const double *img, const int64_t *dim, const double *sigma, double *out)
+{
+    if (!img || !out || !dims_ok(dim) || !sigma)
+        return ORC_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!(sigma[k] >= 0.0))
+            return ORC_EINVAL;
+    const int64_t N = dim[0] * dim[1] * dim[2];
+    memcpy(out, img, sizeof(double) * (size_t)N);
+    if (N == 0)
+        return ORC_OK;
+    for (int k = 0; k < 3; ++k)
+        smooth_axis(out, dim, k, sigma[k]);
+    return ORC_OK;
+}

@@ -686,3 +686,59 @@ def test_occlusion_draw_covers_every_slice_equally():
     freq = ((draws[:, :1] <= z) & (z <= draws[:, 1:])).mean(0)
     p = (dmax / 2) / (zmax + dmax)
     assert np.abs(freq - p).max() < 5 * np.sqrt(p * (1 - p) / n)
+
+
+# ---------------------------------------------------------------------------
+# Resampling pre-step: Gaussian smoothing (Pre- and post-processing section)
+# ---------------------------------------------------------------------------
+
+def test_resample_sigma_formula_examples():
+    """sigma_k = max(r / u_k - 1, 0) / 3: no smoothing when the target is not
+    coarser, 1 voxel when the target is 4x coarser."""
+    np.testing.assert_allclose(oracle.resample_sigma([3.0, 0.75, 6.0], 3.0), [0.0, 1.0, 0.0])
+    np.testing.assert_allclose(oracle.resample_sigma([0.5, 1.5, 2.5], 3.0),
+                               [5.0 / 3.0, 1.0 / 3.0, 0.2 / 3.0], rtol=1e-15)
+
+
+def test_gaussian_smooth_zero_sigma_is_identity_and_constants_stay():
+    rng = np.random.default_rng(3)
+    v = rng.normal(0, 100, (9, 7, 11))
+    np.testing.assert_array_equal(oracle.gaussian_smooth(v, [0, 0, 0]), v)
+    c = np.full((8, 9, 10), -321.5)
+    np.testing.assert_allclose(oracle.gaussian_smooth(c, [2.0, 1.3, 0.7]), c, rtol=1e-14)
+
+
+def test_gaussian_smooth_impulse_is_normalised_kernel():
+    """An interior impulse spreads into the outer product of the normalised
+    1-D kernels exp(-d^2 / sigma^2), |d| <= floor(3 sigma / sqrt 2 + 0.5)."""
+    sig = [1.7, 0.9, 2.6]
+    v = np.zeros((21, 17, 25))
+    v[10, 8, 12] = 1.0
+    out = oracle.gaussian_smooth(v, sig)
+    ks = []
+    for s_ in sig:
+        R = int(np.floor(3 * s_ / np.sqrt(2) + 0.5))
+        d = np.arange(-R, R + 1)
+        k = np.exp(-d.astype(float) ** 2 / s_ ** 2)
+        ks.append(k / k.sum())
+    ref = np.zeros_like(v)
+    Rs = [(len(k) - 1) // 2 for k in ks]
+    ref[10 - Rs[0]:10 + Rs[0] + 1, 8 - Rs[1]:8 + Rs[1] + 1, 12 - Rs[2]:12 + Rs[2] + 1] = \
+        np.einsum("i,j,k->ijk", *ks)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("sig", [(1.2, 0.0, 2.2), (0.45, 3.1, 0.8)])
+def test_gaussian_smooth_matches_scipy_nearest(sig):
+    """exp(-d^2/sigma^2) is a Gaussian of standard deviation sigma / sqrt 2;
+    SciPy's gaussian_filter with that deviation, truncate=3 (the same radius)
+    and mode 'nearest' (edge repeat) computes the same sums."""
+    from scipy import ndimage
+    rng = np.random.default_rng(17)
+    v = rng.normal(0, 300, (14, 12, 19))
+    sd = [s_ / np.sqrt(2) for s_ in sig]
+    ref = v.copy()
+    for ax, s_ in enumerate(sd):
+        if s_ > 0:
+            ref = ndimage.gaussian_filter1d(ref, s_, axis=ax, mode="nearest", truncate=3.0)
+    np.testing.assert_allclose(oracle.gaussian_smooth(v, sig), ref, rtol=1e-12, atol=1e-10)
