@@ -259,6 +259,34 @@ ctaug_status ctaug_bspline_upsample_adjoint(const float *grad_disp, const int64_
                                             size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Resampling pre-step (Sec. "Pre- and post-processing")                     */
+/* ------------------------------------------------------------------------ */
+
+/* Smoothing widths before resampling a volume of voxel spacing spacing[k]
+ * (any unit) to the coarser spacing `target` (same unit):
+ *     sigma_k = max(target / spacing_k - 1, 0) / 3   (input voxels)
+ * Host only.  Errors: EINVAL (null pointer, non-finite or non-positive
+ * spacing or target). */
+ctaug_status ctaug_resample_sigma(const double spacing[3], double target, float sigma[3]);
+
+/* Separable Gaussian smoothing g(x) ~ exp(-sum_k x_k^2 / sigma_k^2) (the
+ * section's kernel as printed: standard deviation sigma_k / sqrt(2) per axis),
+ * sampled at integer offsets |d| <= R_k = floor(3 sigma_k / sqrt(2) + 0.5) and
+ * normalised to sum 1; voxels beyond the volume repeat the nearest edge voxel;
+ * an axis with R_k = 0 is left unchanged.  Resampling itself is then
+ * ctaug_warp_affine with A = diag(target / spacing) (ctaug_affine_matrix with
+ * those scale factors aligns the volume centres).
+ * in: device F32 or I16; out: device F32 with in's dims, not aliasing in;
+ * ws: device workspace of ctaug_gaussian_smooth_workspace(dims) bytes, needed
+ * when two or more axes are smoothed (else may be NULL).  X and Y extents up
+ * to 65535.  FP32 accumulation.
+ * Errors: EINVAL (bad sigma, R_k > 160, aliasing), EDTYPE, ESHAPE,
+ * EWORKSPACE, EHIP. */
+size_t ctaug_gaussian_smooth_workspace(const int64_t dim[3]);
+ctaug_status ctaug_gaussian_smooth(const ctaug_vol *in, ctaug_vol *out, const float sigma[3],
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched augmentation of volumes of uneven sizes (the paper augments a     */
 /* whole training batch through a job queue; here one launch covers it)      */
 /* ------------------------------------------------------------------------ */

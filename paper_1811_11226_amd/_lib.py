@@ -94,6 +94,9 @@ SIGNATURES = {
     "ctaug_batch_plan_get_tuning": (_S, [_P, ctypes.POINTER(Tuning)]),
     "ctaug_batch_plan_destroy": (_S, [_P]),
     "ctaug_copy": (_S, [_P, _P, ctypes.c_size_t, _P]),
+    "ctaug_resample_sigma": (_S, [_PD, ctypes.c_double, _PF]),
+    "ctaug_gaussian_smooth_workspace": (ctypes.c_size_t, [_PI64]),
+    "ctaug_gaussian_smooth": (_S, [_PV, _PV, _PF, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None

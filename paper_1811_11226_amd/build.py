@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libctaug.so")
-SOURCES = ["api.hip", "warp_fwd.hip", "warp_bwd.hip", "bspline.hip"]
+SOURCES = ["api.hip", "warp_fwd.hip", "warp_bwd.hip", "bspline.hip", "smooth.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -502,6 +502,83 @@ extern "C" ctaug_status ctaug_bspline_upsample_adjoint(const float *grad_disp,
 }
 
 // ---------------------------------------------------------------------------
+// Resampling pre-step
+// ---------------------------------------------------------------------------
+
+extern "C" ctaug_status ctaug_resample_sigma(const double spacing[3], double target,
+                                             float sigma[3])
+{
+    if (!spacing || !sigma || !std::isfinite(target) || !(target > 0.0))
+        return CTAUG_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(spacing[k]) || !(spacing[k] > 0.0))
+            return CTAUG_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        sigma[k] = (float)std::max((target / spacing[k] - 1.0) / 3.0, 0.0);
+    return CTAUG_OK;
+}
+
+extern "C" size_t ctaug_gaussian_smooth_workspace(const int64_t dim[3])
+{
+    if (!dim || !dims_valid(dim))
+        return 0;
+    return (size_t)nelem(dim) * sizeof(float);
+}
+
+extern "C" ctaug_status ctaug_gaussian_smooth(const ctaug_vol *in, ctaug_vol *out,
+                                              const float sigma[3], void *ws, size_t ws_bytes,
+                                              void *stream)
+{
+    ctaug_status st;
+    if ((st = check_vol(in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+        return st;
+    if ((st = check_vol(out, 1u << CTAUG_F32)) != CTAUG_OK)
+        return st;
+    if (!same_dims(in, out))
+        return CTAUG_ESHAPE;
+    if (!sigma)
+        return CTAUG_EINVAL;
+    int active[3], m = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(sigma[k]) || sigma[k] < 0.0f)
+            return CTAUG_EINVAL;
+        if (gauss_radius(sigma[k]) > kMaxGaussRadius)
+            return CTAUG_EINVAL;
+        if (gauss_radius(sigma[k]) > 0)
+            active[m++] = k;
+    }
+    const int64_t n = nelem(in->dim);
+    if (n == 0)
+        return CTAUG_OK;
+    if (in->dim[0] > 65535 || in->dim[1] > 65535)
+        return CTAUG_ESHAPE;               // grid y / z extents
+    if (in->data == out->data)
+        return CTAUG_EINVAL;               // out must not alias in
+    if (m >= 2 && (!ws || ws_bytes < (size_t)n * sizeof(float)))
+        return CTAUG_EWORKSPACE;
+    const int32_t d[3] = {(int32_t)in->dim[0], (int32_t)in->dim[1], (int32_t)in->dim[2]};
+    hipStream_t s = as_stream(stream);
+    float *dst = static_cast<float *>(out->data);
+    float *tmp = static_cast<float *>(ws);
+    if (m == 0)                            // no smoothing: a converting copy
+        return hip_status(launch_smooth_axis(in->data, in->dtype == CTAUG_I16, dst, d, 2,
+                                             gauss_taps(0.0f), s));
+    // ping-pong so that the last pass writes `out`
+    const void *src = in->data;
+    bool src_i16 = in->dtype == CTAUG_I16;
+    for (int p = 0; p < m; ++p) {
+        float *o = ((m - 1 - p) % 2 == 0) ? dst : tmp;
+        hipError_t e = launch_smooth_axis(src, src_i16, o, d, active[p],
+                                          gauss_taps(sigma[active[p]]), s);
+        if (e != hipSuccess)
+            return CTAUG_EHIP;
+        src = o;
+        src_i16 = false;
+    }
+    return CTAUG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Batch plan
 // ---------------------------------------------------------------------------
 

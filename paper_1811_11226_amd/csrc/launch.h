@@ -43,4 +43,15 @@ hipError_t launch_bspline_up(const float *ctrl, const int64_t G[3], const int64_
 hipError_t launch_bspline_adj(const float *grad_disp, const int64_t od[3], const int64_t G[3],
                               float *grad_ctrl, double *ws, hipStream_t s);
 
+// Gaussian smoothing of the resampling pre-step.
+constexpr int kMaxGaussRadius = 160;
+struct GaussTaps {
+    int32_t R;                         // taps at offsets -R .. R
+    float w[kMaxGaussRadius + 1];      // w[|d|], normalised to sum 1 over -R .. R
+};
+int32_t gauss_radius(float sigma);
+GaussTaps gauss_taps(float sigma);
+hipError_t launch_smooth_axis(const void *in, bool in_i16, float *out, const int32_t dim[3],
+                              int axis, const GaussTaps &K, hipStream_t s);
+
 }  // namespace ctaug

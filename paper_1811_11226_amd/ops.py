@@ -353,3 +353,32 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# -- resampling pre-step ------------------------------------------------------
+
+def resample_sigma(spacing, target):
+    """Smoothing widths (input voxels) before resampling from voxel spacing
+    `spacing` (3 values) to `target`."""
+    sp = (ctypes.c_double * 3)(*[float(v) for v in spacing])
+    out = (ctypes.c_float * 3)()
+    _lib.check(_lib.load().ctaug_resample_sigma(sp, float(target), out), "ctaug_resample_sigma")
+    return tuple(out[:])
+
+
+def gaussian_smooth(volume, sigma, out=None):
+    """Separable Gaussian smoothing of a float32 / int16 volume into float32."""
+    _require(volume, "volume", (torch.float32, torch.int16))
+    if out is None:
+        out = torch.empty(tuple(volume.shape), dtype=torch.float32, device=volume.device)
+    _require(out, "out", (torch.float32,))
+    L = _lib.load()
+    d = (ctypes.c_int64 * 3)(*volume.shape)
+    ws_bytes = int(L.ctaug_gaussian_smooth_workspace(d))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=volume.device)
+    sg = (ctypes.c_float * 3)(*[float(v) for v in sigma])
+    vi, vo = vol(volume), vol(out)
+    _lib.check(L.ctaug_gaussian_smooth(ctypes.byref(vi), ctypes.byref(vo), sg,
+                                       ctypes.c_void_p(ws.data_ptr()), ws_bytes, _stream()),
+               "ctaug_gaussian_smooth")
+    return out

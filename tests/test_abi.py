@@ -320,3 +320,37 @@ def test_plan_calls_reject_null_plan(L):
     assert L.ctaug_batch_plan_replay(None, None) == EINVAL
     assert L.ctaug_batch_plan_update(None, None) == EINVAL
     assert L.ctaug_batch_plan_autotune(None, None, 0, 1, None, None, None) == EINVAL
+
+
+# -- resampling pre-step ----------------------------------------------------------
+
+@pytest.mark.parametrize("spacing,target", [((0.7, 0.7, 2.5), 3.0), ((3.0, 1.0, 0.4), 3.0),
+                                            ((5.0, 6.0, 7.0), 3.0)])
+def test_resample_sigma_matches_oracle(L, spacing, target):
+    sp = (ctypes.c_double * 3)(*spacing)
+    out = (ctypes.c_float * 3)()
+    assert L.ctaug_resample_sigma(sp, target, out) == OK
+    np.testing.assert_array_equal(np.array(out[:], dtype=np.float32),
+                                  oracle.resample_sigma(spacing, target).astype(np.float32))
+
+
+def test_smoothing_validation(L):
+    r = ctypes.byref
+    sg = (ctypes.c_float * 3)(1.0, 1.0, 0.0)
+    a, b = vol((8, 8, 8)), vol((8, 8, 8), data=0x2000)
+    assert L.ctaug_resample_sigma(None, 3.0, sg) == EINVAL
+    assert L.ctaug_resample_sigma((ctypes.c_double * 3)(1, 0, 1), 3.0, sg) == EINVAL
+    assert L.ctaug_resample_sigma((ctypes.c_double * 3)(1, 1, 1), math.nan, sg) == EINVAL
+    assert L.ctaug_gaussian_smooth(r(a), r(b), None, None, 0, None) == EINVAL
+    assert L.ctaug_gaussian_smooth(r(a), r(vol((8, 8, 9), data=0x2000)), sg, None, 0,
+                                   None) == ESHAPE
+    assert L.ctaug_gaussian_smooth(r(a), r(vol((8, 8, 8), I16, data=0x2000)), sg, None, 0,
+                                   None) == EDTYPE
+    assert L.ctaug_gaussian_smooth(r(a), r(a), sg, None, 0, None) == EINVAL          # aliasing
+    assert L.ctaug_gaussian_smooth(r(a), r(b), sg, None, 0, None) == EWORKSPACE      # 2 axes
+    assert L.ctaug_gaussian_smooth(r(a), r(b), (ctypes.c_float * 3)(-1, 0, 0), None, 0,
+                                   None) == EINVAL
+    assert L.ctaug_gaussian_smooth(r(a), r(b), (ctypes.c_float * 3)(500, 0, 0), None, 0,
+                                   None) == EINVAL                                   # R > 160
+    need = L.ctaug_gaussian_smooth_workspace((ctypes.c_int64 * 3)(8, 8, 8))
+    assert need == 8 * 8 * 8 * 4

@@ -498,6 +498,40 @@ def test_autograd_affine_and_nonrigid_chain():
     assert_grad(_np(c.grad), oracle.bspline_adjoint(r_u, (6, 6, 6)), "autograd g_ctrl")
 
 
+@pytest.mark.parametrize("dims,sigma,dtype", [((30, 26, 41), (1.4, 0.0, 2.3), np.float32),
+                                              ((17, 33, 20), (0.9, 1.9, 0.6), np.int16),
+                                              ((9, 11, 64), (0.0, 0.0, 4.7), np.float32),
+                                              ((12, 10, 14), (0.0, 0.0, 0.0), np.int16)])
+def test_gaussian_smooth_parity(dims, sigma, dtype):
+    rng = np.random.default_rng(int(sum(dims)))
+    v = np.round(rng.normal(0, 400, dims)).astype(dtype)
+    out = _np(ctaug.gaussian_smooth(_t(v), sigma))
+    ref = oracle.gaussian_smooth(v, sigma)
+    assert_intensity(out, ref, windowed=False, what=f"smooth {sigma}")
+
+
+def test_resampling_pipeline_parity():
+    """Resample to a coarser target spacing: smooth with the section's widths,
+    then trilinear warp with A = diag(target / spacing) about the centres."""
+    spacing, target = (0.8, 0.75, 2.0), 3.0
+    in_dim = (60, 64, 24)
+    img, lbl = phantom_pair(in_dim, seed=41)
+    scale = [target / s_ for s_ in spacing]
+    out_dim = tuple(int(np.floor(n * s_ / target)) for n, s_ in zip(in_dim, spacing))
+    prm = identity_affine_params()
+    prm[3:6] = scale
+    sig = ctaug.resample_sigma(spacing, target)
+    np.testing.assert_allclose(sig, oracle.resample_sigma(spacing, target), rtol=1e-7)
+    sm = ctaug.gaussian_smooth(_t(img), sig)
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    out, lout = ctaug.warp_affine(sm, M, lbl=_t(lbl), out_dim=out_dim)
+    ref_sm = oracle.gaussian_smooth(img, np.asarray(sig, dtype=np.float64))
+    ref, lref = oracle.warp(_np(sm), M, out_dim, lbl=lbl)
+    assert_intensity(_np(sm), ref_sm, windowed=False, what="smoothed")
+    assert_intensity(_np(out), ref, windowed=False, what="resampled")
+    assert np.array_equal(_np(lout), lref)
+
+
 # ---------------------------------------------------------------------------
 # Batched persistent launch and HIP graph replay
 # ---------------------------------------------------------------------------
