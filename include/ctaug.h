@@ -249,6 +249,21 @@ ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in, const flo
 ctaug_status ctaug_bspline_upsample(const float *ctrl, const int64_t G[3],
                                     const int64_t out_dim[3], float *disp, void *stream);
 
+/* Fused nonrigid warp: ctaug_warp_displacement with the displacement of
+ * ctaug_bspline_upsample(ctrl, G, img_out dims) evaluated inside the warp
+ * kernel instead of read from a dense field (the nonrigid deformation the
+ * paper applies on top of the affine map, built from a coarse control grid).
+ * The field is computed with the same FP32 operations in the same order as
+ * ctaug_bspline_upsample, so outputs and labels equal those of the two
+ * unfused calls bit for bit; no field is stored.  ctrl: device float
+ * [3][Gx][Gy][Gz] with 4 <= G_k <= 64; other arguments as ctaug_warp_affine.
+ * Errors: as ctaug_warp_affine, plus EINVAL for a NULL ctrl with a nonempty
+ * output and ESHAPE for a bad grid. */
+ctaug_status ctaug_warp_bspline(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
+                                const float M[12], const float *ctrl, const int64_t G[3],
+                                float fill, int32_t label_fill, const ctaug_photo *photo,
+                                ctaug_vol *img_out, ctaug_vol *lbl_out, void *stream);
+
 /* Workspace bytes for ctaug_bspline_upsample_adjoint. */
 size_t ctaug_bspline_adjoint_workspace(const int64_t out_dim[3], const int64_t G[3]);
 

@@ -70,6 +70,8 @@ SIGNATURES = {
                                ctypes.POINTER(Photo), _PV, _PV, _P]),
     "ctaug_warp_displacement": (_S, [_PV, _PV, _PF, _P, ctypes.c_float, ctypes.c_int32,
                                      ctypes.POINTER(Photo), _PV, _PV, _P]),
+    "ctaug_warp_bspline": (_S, [_PV, _PV, _PF, _P, _PI64, ctypes.c_float, ctypes.c_int32,
+                                ctypes.POINTER(Photo), _PV, _PV, _P]),
     "ctaug_photometric_noise": (_S, [_PV, ctypes.POINTER(Photo), _P]),
     "ctaug_noise": (_S, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, _P,
                          _P, _P]),

@@ -308,6 +308,25 @@ extern "C" ctaug_status ctaug_affine_matrix(const ctaug_affine_params *p, const 
     return CTAUG_OK;
 }
 
+static bool grid_valid(const int64_t G[3])
+{
+    if (!G)
+        return false;
+    for (int i = 0; i < 3; ++i)
+        if (G[i] < 4 || G[i] > bspline_max_grid())
+            return false;
+    return true;
+}
+
+static ctaug_status check_grid(const int64_t G[3], const int64_t od[3])
+{
+    if (!G || !od)
+        return CTAUG_EINVAL;
+    if (!dims_valid(od) || 3 * nelem(od) > kMaxElems)
+        return CTAUG_ESHAPE;
+    return grid_valid(G) ? CTAUG_OK : CTAUG_ESHAPE;
+}
+
 static ctaug_status warp_impl(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const float M[12],
                               const float *disp, bool need_disp, float fill, int32_t label_fill,
                               const ctaug_photo *photo, ctaug_vol *img_out, ctaug_vol *lbl_out,
@@ -340,6 +359,30 @@ extern "C" ctaug_status ctaug_warp_displacement(const ctaug_vol *img_in, const c
 {
     return warp_impl(img_in, lbl_in, M, disp, true, fill, label_fill, photo, img_out, lbl_out,
                      stream);
+}
+
+extern "C" ctaug_status ctaug_warp_bspline(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
+                                           const float M[12], const float *ctrl,
+                                           const int64_t G[3], float fill, int32_t label_fill,
+                                           const ctaug_photo *photo, ctaug_vol *img_out,
+                                           ctaug_vol *lbl_out, void *stream)
+{
+    FwdJob J;
+    ctaug_status st = make_job(img_in, lbl_in, M, nullptr, false, fill, label_fill, photo,
+                               img_out, lbl_out, kDefaultTiling, J);
+    if (st != CTAUG_OK)
+        return st;
+    if (!G)
+        return CTAUG_EINVAL;
+    if (!grid_valid(G))
+        return CTAUG_ESHAPE;
+    if (empty(J))
+        return CTAUG_OK;
+    if (!ctrl)
+        return CTAUG_EINVAL;
+    J.ctrl = ctrl;
+    J.bs = bspline_geom(G, img_out->dim);
+    return hip_status(launch_warp_single(J, kDefaultTiling, as_stream(stream)));
 }
 
 extern "C" ctaug_status ctaug_photometric_noise(ctaug_vol *inout, const ctaug_photo *photo,
@@ -449,18 +492,6 @@ extern "C" ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in
 {
     return backward_impl(img_in, M, disp, true, fill, grad_out, grad_img, grad_M, grad_disp, ws,
                          ws_bytes, stream);
-}
-
-static ctaug_status check_grid(const int64_t G[3], const int64_t od[3])
-{
-    if (!G || !od)
-        return CTAUG_EINVAL;
-    if (!dims_valid(od) || 3 * nelem(od) > kMaxElems)
-        return CTAUG_ESHAPE;
-    for (int i = 0; i < 3; ++i)
-        if (G[i] < 4 || G[i] > bspline_max_grid())
-            return CTAUG_ESHAPE;
-    return CTAUG_OK;
 }
 
 extern "C" ctaug_status ctaug_bspline_upsample(const float *ctrl, const int64_t G[3],

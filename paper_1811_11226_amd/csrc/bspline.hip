@@ -5,6 +5,7 @@
 // the same factorisation backwards, one axis per pass (z in FP32 per row,
 // then y and x in FP64, each in a fixed order), so the control-grid gradient
 // is deterministic.
+#include "bspline_eval.h"
 #include "device_common.h"
 #include "launch.h"
 
@@ -12,30 +13,6 @@ namespace ctaug {
 
 constexpr int kRowsPerWG = 4;          // upsample: rows (x, y..y+3) per workgroup
 constexpr int kMaxG = 64;
-
-struct BsplineGeom {
-    int32_t ox, oy, oz;
-    int32_t gx, gy, gz;
-    float inv_hx, inv_hy, inv_hz;      // (G - 3) / (n - 1), or 0 when n == 1
-};
-
-__device__ __forceinline__ void bs_cell(int32_t p, float inv_h, int32_t G, int32_t &i, float &t)
-{
-    const float s = (float)p * inv_h;
-    const float f = fminf(floorf(s), (float)(G - 4));
-    i = (int32_t)f;
-    t = s - f;
-}
-
-__device__ __forceinline__ void bs_basis(float t, float B[4])
-{
-    const float t2 = t * t, t3 = t2 * t, m = 1.0f - t;
-    const float sixth = 1.0f / 6.0f;
-    B[0] = m * m * m * sixth;
-    B[1] = __builtin_fmaf(3.0f, t3, __builtin_fmaf(-6.0f, t2, 4.0f)) * sixth;
-    B[2] = __builtin_fmaf(-3.0f, t3, __builtin_fmaf(3.0f, t2, __builtin_fmaf(3.0f, t, 1.0f))) * sixth;
-    B[3] = t3 * sixth;
-}
 
 __global__ __launch_bounds__(kThreads) void k_bspline_up(const float *__restrict__ ctrl,
                                                          BsplineGeom G, float *__restrict__ disp,
@@ -45,31 +22,13 @@ __global__ __launch_bounds__(kThreads) void k_bspline_up(const float *__restrict
     const int x = blockIdx.x;
     const int y0 = blockIdx.y * kRowsPerWG;
     const int64_t nvox = (int64_t)G.ox * G.oy * G.oz;
-    const int64_t gstride = (int64_t)G.gx * G.gy * G.gz;
 
-    int32_t ix;
-    float tx, Bx[4];
-    bs_cell(x, G.inv_hx, G.gx, ix, tx);
-    bs_basis(tx, Bx);
     for (int e = threadIdx.x; e < kRowsPerWG * 3 * G.gz; e += kThreads) {
         const int row = e / (3 * G.gz);
         const int rem = e - row * 3 * G.gz;
         const int comp = rem / G.gz, gz = rem - comp * G.gz;
         const int y = min(y0 + row, G.oy - 1);
-        int32_t iy;
-        float ty, By[4];
-        bs_cell(y, G.inv_hy, G.gy, iy, ty);
-        bs_basis(ty, By);
-        float s = 0.0f;
-        for (int a = 0; a < 4; ++a) {
-            float sa = 0.0f;
-            for (int b = 0; b < 4; ++b)
-                sa = __builtin_fmaf(By[b],
-                                    ctrl[comp * gstride + ((int64_t)(ix + a) * G.gy + (iy + b)) * G.gz + gz],
-                                    sa);
-            s = __builtin_fmaf(Bx[a], sa, s);
-        }
-        P[row][comp][gz] = s;
+        P[row][comp][gz] = bs_profile(ctrl, G, comp, x, y, gz);
     }
     __syncthreads();
 
@@ -110,9 +69,6 @@ __global__ __launch_bounds__(kThreads) void k_bspline_up(const float *__restrict
     }
 }
 
-// Adjoint, stage 1: for output plane x and a chunk of kAdjRows rows,
-//   R[comp][gy][gz] = sum_{y in chunk} sum_z By_{gy-iy(y)} Bz_{gz-iz(z)} g[comp](x,y,z)
-// written in FP64 to ws[x][chunk][comp][gy][gz].
 // Adjoint, pass 1 (z): T1[comp][x][y][gz] = sum_z B_{gz - iz(z)}(t(z)) g[comp][x][y][z],
 // one thread per (comp, x, y) row streaming z with 16-byte loads when the
 // rows are aligned.  The z-cell index is nondecreasing along the row, so the
@@ -219,21 +175,6 @@ __global__ __launch_bounds__(kThreads) void k_bspline_adj_x(const double *__rest
     grad_ctrl[e] = (float)s;
 }
 
-static BsplineGeom geom(const int64_t G[3], const int64_t od[3])
-{
-    BsplineGeom g;
-    g.ox = (int32_t)od[0];
-    g.oy = (int32_t)od[1];
-    g.oz = (int32_t)od[2];
-    g.gx = (int32_t)G[0];
-    g.gy = (int32_t)G[1];
-    g.gz = (int32_t)G[2];
-    g.inv_hx = od[0] > 1 ? (float)((double)(G[0] - 3) / (double)(od[0] - 1)) : 0.0f;
-    g.inv_hy = od[1] > 1 ? (float)((double)(G[1] - 3) / (double)(od[1] - 1)) : 0.0f;
-    g.inv_hz = od[2] > 1 ? (float)((double)(G[2] - 3) / (double)(od[2] - 1)) : 0.0f;
-    return g;
-}
-
 int bspline_max_grid() { return kMaxG; }
 
 // Workspace of the adjoint: T1 (FP32, 3 x ox x oy x Gz), then T2 (FP64,
@@ -253,7 +194,7 @@ hipError_t launch_bspline_up(const float *ctrl, const int64_t G[3], const int64_
 {
     if (od[0] == 0 || od[1] == 0 || od[2] == 0)
         return hipSuccess;
-    const BsplineGeom g = geom(G, od);
+    const BsplineGeom g = bspline_geom(G, od);
     dim3 grid((unsigned)od[0], (unsigned)((od[1] + kRowsPerWG - 1) / kRowsPerWG));
     hipLaunchKernelGGL(k_bspline_up, grid, dim3(kThreads), 0, s, ctrl, g, disp, vec ? 1 : 0);
     return hipGetLastError();
@@ -262,7 +203,7 @@ hipError_t launch_bspline_up(const float *ctrl, const int64_t G[3], const int64_
 hipError_t launch_bspline_adj(const float *grad_disp, const int64_t od[3], const int64_t G[3],
                               float *grad_ctrl, double *ws, hipStream_t s)
 {
-    BsplineGeom g = geom(G, od);
+    BsplineGeom g = bspline_geom(G, od);
     if (od[0] == 0 || od[1] == 0 || od[2] == 0)
         g.ox = 0;                      // no voxels: every control gradient is 0
     float *T1 = reinterpret_cast<float *>(ws);

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bspline_eval.h"
+
 namespace ctaug {
 
 constexpr int kThreads = 256;          // workgroup size of every warp kernel
@@ -30,6 +32,10 @@ enum : uint32_t {
 
 enum : int32_t { kF32 = 0, kI16 = 1, kI8 = 2 };
 
+// Source of the per-voxel displacement of a warp: none (affine), a dense
+// field, or the cubic B-spline of a control grid evaluated in the kernel.
+enum : int { kDispNone = 0, kDispField = 1, kDispSpline = 2 };
+
 // One forward warp job as the kernels see it.  Built on the host from the
 // public arguments; lives in kernel arguments (single calls) or in a device
 // table (batched calls).
@@ -39,6 +45,9 @@ struct FwdJob {
     float *out;                        // F32 [ox][oy][oz]
     int8_t *lout;                      // I8 [ox][oy][oz] or null
     const float *disp;                 // F32 SoA [3][ox][oy][oz] or null
+    const float *ctrl;                 // F32 control grid [3][gx][gy][gz] or null; the
+                                       // displacement is evaluated from it in the kernel
+    BsplineGeom bs;                    // geometry of ctrl over the output
     int32_t dtype;
     int32_t nx, ny, nz;
     int32_t ox, oy, oz;

@@ -31,24 +31,31 @@ namespace ctaug {
 enum : int { kPathOutside, kPathLdsInterior, kPathLdsBoundary, kPathDirectInterior,
              kPathDirectBoundary };
 
+// Sample coordinates of one thread's run, computed once by a displacement
+// tile (which needs them to bound its footprint) and reused for sampling.
+struct RunQ {
+    float q[3][4];
+};
+
 // All runs of one tile along one sampling path.  Each thread owns runs of 4
-// consecutive output voxels along z.
-template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL, bool DISP>
+// consecutive output voxels along z.  With a displacement (DISP) the tile has
+// exactly one run per thread and its coordinates come precomputed in Q.
+template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL, int DISP>
 __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &SL,
-                                         const LT *s_img, const int8_t *s_lbl)
+                                         const LT *s_img, const int8_t *s_lbl, const RunQ &Q)
 {
     const Src S = make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz);
     gmut<float> *out = gm<float>(J.out);
     gmut<int8_t> *lout = gm<int8_t>(J.lout);
-    gconst<float> *disp = gc<float>(J.disp);
     Photo P = photo_of(J);
-    const int32_t nvox = J.ox * J.oy * J.oz;
     const int runs_z_log = SL.lz - 2;
     const int nruns = 1 << (SL.lx + SL.ly + runs_z_log);
     const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
     const int8_t lfill = (int8_t)J.label_fill;
 
     for (int r = threadIdx.x; r < nruns; r += kThreads) {
+        if (DISP != kDispNone && r != (int)threadIdx.x)
+            break;
         const int zr = r & ((1 << runs_z_log) - 1);
         const int rr = r >> runs_z_log;
         const int y = G.y0 + (rr & ((1 << SL.ly) - 1));
@@ -81,10 +88,10 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
             const float zf = (float)(z + k);
             float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
                   qz = coord(J.M, 2, rb, zf);
-            if (DISP) {
-                qx = qx + disp[v0 + k];
-                qy = qy + disp[nvox + v0 + k];
-                qz = qz + disp[2 * nvox + v0 + k];
+            if (DISP != kDispNone) {
+                qx = Q.q[0][k];
+                qy = Q.q[1][k];
+                qz = Q.q[2][k];
             }
             if (PATH == kPathLdsInterior || PATH == kPathLdsBoundary) {
                 if (PATH == kPathLdsBoundary && !in_guard(qx, qy, qz, J.nx, J.ny, J.nz))
@@ -170,37 +177,103 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
 // group and (with 16-byte aligned outputs) one vector store.  LT: type of the
 // LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
 // the LDS reads).
-template <typename T, typename LT, bool ALIGNED, bool LBL, bool DISP>
+template <typename T, typename LT, bool ALIGNED, bool LBL, int DISP>
 __device__ __forceinline__ void fwd_box_l(const FwdJob &J, const TileGeom &G, const Tiling &SL,
-                                         uint8_t *s_lds, int32_t lds_cells)
+                                         uint8_t *s_lds, int32_t lds_cells, const RunQ &Q)
 {
     LT *s_img = reinterpret_cast<LT *>(s_lds);
     int8_t *s_lbl = reinterpret_cast<int8_t *>(s_lds + lds_label_offset<LT>(lds_cells));
     if (G.cls == kOutside) {
-        run_tile<T, LT, kPathOutside, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathOutside, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
     } else if (G.lds) {
         stage_footprint<T, LT>(J, make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz), G, s_img, s_lbl);
         __syncthreads();
         if (G.cls == kInterior)
-            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
         else
-            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
+            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
         __syncthreads();               // LDS is reused by the next box
     } else if (G.cls == kInterior) {
-        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
     } else {
-        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl);
+        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
     }
 }
 
-template <typename T, typename LT, bool ALIGNED, bool DISP>
+template <typename T, typename LT, bool ALIGNED, int DISP>
 __device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, const Tiling &SL,
-                                       uint8_t *s_lds, int32_t lds_cells)
+                                       uint8_t *s_lds, int32_t lds_cells, const RunQ &Q)
 {
     if (J.flags & kFlagLabels)
-        fwd_box_l<T, LT, ALIGNED, true, DISP>(J, G, SL, s_lds, lds_cells);
+        fwd_box_l<T, LT, ALIGNED, true, DISP>(J, G, SL, s_lds, lds_cells, Q);
     else
-        fwd_box_l<T, LT, ALIGNED, false, DISP>(J, G, SL, s_lds, lds_cells);
+        fwd_box_l<T, LT, ALIGNED, false, DISP>(J, G, SL, s_lds, lds_cells, Q);
+}
+
+// Displacement of the runs of a displacement tile evaluated from the control
+// grid.  The row profiles of the tile's rows over its z-control window go to
+// LDS (free until the footprint is staged); each thread then contracts z for
+// its own voxels.  The operations and their order are those of the upsampling
+// kernel, so u equals the dense field bit for bit.  A window of more than
+// kProfCtrl controls (controls closer than about 4 voxels along z) evaluates
+// the profiles per voxel instead.
+constexpr int kProfCtrl = 8;
+
+__device__ __forceinline__ void spline_u(const FwdJob &J, const Tiling &TL, int x0, int y0, int z0,
+                                         int x1, int y1, int z1, int rr, int x, int y, int z,
+                                         int nvalid, bool mine, float *s_prof, float (&u)[3][4])
+{
+    const BsplineGeom &B = J.bs;
+    const int izl = bs_index(z0, B.inv_hz, B.gz);
+    const int ncz = bs_index(z1, B.inv_hz, B.gz) - izl + 4;
+    if (ncz <= kProfCtrl) {
+        const int per_row = 3 * ncz;
+        const int nent = per_row << (TL.lx + TL.ly);
+        for (int e = threadIdx.x; e < nent; e += kThreads) {
+            const int row = e / per_row;
+            const int rem = e - row * per_row;
+            const int comp = rem / ncz, c = rem - comp * ncz;
+            const int px = min(x0 + (row >> TL.ly), x1);
+            const int py = min(y0 + (row & ((1 << TL.ly) - 1)), y1);
+            s_prof[e] = bs_profile(J.ctrl, B, comp, px, py, izl + c);
+        }
+        __syncthreads();
+        if (!mine)
+            return;
+        const float *P = s_prof + rr * per_row - izl;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= nvalid)
+                break;
+            int32_t iz;
+            float tz, Bz[4];
+            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
+            bs_basis(tz, Bz);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                float s = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    s = __builtin_fmaf(Bz[c], P[comp * ncz + iz + c], s);
+                u[comp][k] = s;
+            }
+        }
+    } else if (mine) {
+        for (int k = 0; k < nvalid; ++k) {
+            int32_t iz;
+            float tz, Bz[4];
+            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
+            bs_basis(tz, Bz);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                float s = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    s = __builtin_fmaf(Bz[c], bs_profile(J.ctrl, B, comp, x, y, iz + c), s);
+                u[comp][k] = s;
+            }
+        }
+    }
 }
 
 // One output tile, processed as sub-tiles of the job's sub-tile shape (the
@@ -209,7 +282,7 @@ __device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, cons
 // group and (with 16-byte aligned outputs) one vector store.  LT: type of the
 // LDS footprint cells (FP32, or int16 for int16 inputs: half the LDS, twice
 // the LDS reads).
-template <typename T, typename LT, bool ALIGNED, bool DISP>
+template <typename T, typename LT, bool ALIGNED, int DISP>
 __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling &TL,
                                             int32_t lds_cells, uint8_t *s_lds)
 {
@@ -222,31 +295,44 @@ __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling
     const int y1 = min(y0 + (1 << TL.ly), J.oy) - 1;
     const int z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
     const Tiling SL = {J.sub[0], J.sub[1], J.sub[2]};
-    if (DISP) {
-        // A displacement field has no a-priori footprint bound: the tile (one
-        // run of 4 z voxels per thread) reduces floor(q) over its guarded
-        // samples, and stages that footprint when it fits the reservation.
+    if (DISP != kDispNone) {
+        // A displacement has no a-priori footprint bound: the tile (one run of
+        // 4 z voxels per thread) computes its coordinates once, reduces floor(q)
+        // over its guarded samples, and stages that footprint when it fits the
+        // reservation.
         __shared__ int s_red[kThreads / 64][6];
         const int zr = threadIdx.x & ((1 << (TL.lz - 2)) - 1);
         const int rr = threadIdx.x >> (TL.lz - 2);
         const int x = x0 + (rr >> TL.ly), y = y0 + (rr & ((1 << TL.ly) - 1)), z = z0 + 4 * zr;
+        const bool mine = x <= x1 && y <= y1 && z <= z1;
+        const int nvalid = min(4, J.oz - z);
+        float u[3][4];
+        if (DISP == kDispSpline)
+            spline_u(J, TL, x0, y0, z0, x1, y1, z1, rr, x, y, z, nvalid, mine,
+                     reinterpret_cast<float *>(s_lds), u);
+        RunQ Q;
         int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
-        if (x <= x1 && y <= y1 && z <= z1 && J.nx > 0 && J.ny > 0 && J.nz > 0) {
+        if (mine) {
             gconst<float> *disp = gc<float>(J.disp);
             const int32_t nvox = J.ox * J.oy * J.oz;
             const int32_t v0 = (x * J.oy + y) * J.oz + z;
+            const bool any_in = J.nx > 0 && J.ny > 0 && J.nz > 0;
             float rb[3];
             row_base(J.M, (float)x, (float)y, rb);
-            for (int k = 0; k < min(4, J.oz - z); ++k) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= nvalid)
+                    break;
                 const float zf = (float)(z + k);
-                const float q[3] = {coord(J.M, 0, rb, zf) + disp[v0 + k],
-                                    coord(J.M, 1, rb, zf) + disp[nvox + v0 + k],
-                                    coord(J.M, 2, rb, zf) + disp[2 * nvox + v0 + k]};
-                if (!in_guard(q[0], q[1], q[2], J.nx, J.ny, J.nz))
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    Q.q[i][k] = coord(J.M, i, rb, zf) +
+                                (DISP == kDispField ? disp[i * nvox + v0 + k] : u[i][k]);
+                if (!any_in || !in_guard(Q.q[0][k], Q.q[1][k], Q.q[2][k], J.nx, J.ny, J.nz))
                     continue;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const int f = (int)floorf(q[i]);
+                    const int f = (int)floorf(Q.q[i][k]);
                     fmn[i] = min(fmn[i], f);
                     fmx[i] = max(fmx[i], f);
                 }
@@ -256,20 +342,21 @@ __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling
         TileGeom G = geom_from_cells(J, x0, y0, z0, x1, y1, z1, fmn, fmx, lds_cells);
         if (G.lds && (J.flags & kFlagLds16) && !(J.flags & kFlagFillInT))
             G.lds = false;             // an int16 footprint must hold fill exactly
-        fwd_box<T, LT, ALIGNED, true>(J, G, TL, s_lds, lds_cells);
+        fwd_box<T, LT, ALIGNED, DISP>(J, G, TL, s_lds, lds_cells, Q);
         return;
     }
+    const RunQ Q0{};
     for (int sx = x0; sx <= x1; sx += 1 << SL.lx)
         for (int sy = y0; sy <= y1; sy += 1 << SL.ly)
             for (int sz = z0; sz <= z1; sz += 1 << SL.lz) {
                 const TileGeom G = box_geom(J, sx, sy, sz, min(sx + (1 << SL.lx) - 1, x1),
                                             min(sy + (1 << SL.ly) - 1, y1),
                                             min(sz + (1 << SL.lz) - 1, z1), lds_cells);
-                fwd_box<T, LT, ALIGNED, false>(J, G, SL, s_lds, lds_cells);
+                fwd_box<T, LT, ALIGNED, kDispNone>(J, G, SL, s_lds, lds_cells, Q0);
             }
 }
 
-template <typename T, bool ALIGNED, bool DISP>
+template <typename T, bool ALIGNED, int DISP>
 __device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &TL,
                                          int32_t lds_cells, uint8_t *s_lds)
 {
@@ -284,7 +371,7 @@ __device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &T
 extern __shared__ __attribute__((aligned(16))) uint8_t s_footprint[];
 
 // Single job, job in kernel arguments, one workgroup per tile.
-template <typename T, bool ALIGNED, bool DISP>
+template <typename T, bool ALIGNED, int DISP>
 __global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, int32_t ntiles,
                                                           int32_t lds_cells)
 {
@@ -321,15 +408,15 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
         const FwdJob J = jobs[j];
         const int lt = t - prefix[j];
         if (MODE == kBatchI16F32)
-            fwd_tile_lt<int16_t, float, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile_lt<int16_t, float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
         else if (MODE == kBatchI16I16)
-            fwd_tile_lt<int16_t, int16_t, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile_lt<int16_t, int16_t, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
         else if (MODE == kBatchF32)
-            fwd_tile_lt<float, float, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile_lt<float, float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
         else if (J.dtype == kI16)
-            fwd_tile<int16_t, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile<int16_t, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
         else
-            fwd_tile<float, ALIGNED, false>(J, lt, TL, lds_cells, s_footprint);
+            fwd_tile<float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
     }
 }
 
@@ -361,7 +448,7 @@ int32_t footprint_cells_bound(const FwdJob &J, const Tiling &TL)
 // equals; the whole tile (direct gathers) when none fits.
 Tiling choose_subtile(const FwdJob &J, const Tiling &TL, int32_t lds_cells)
 {
-    if (J.disp || lds_cells <= 0 || footprint_cells_bound(J, TL) <= lds_cells)
+    if (J.disp || J.ctrl || lds_cells <= 0 || footprint_cells_bound(J, TL) <= lds_cells)
         return TL;
     const int min_log = std::min(10, TL.lx + TL.ly + TL.lz);
     Tiling best = TL;
@@ -401,7 +488,7 @@ size_t lds_bytes_for(int32_t cells, int32_t elem_bytes)
     return (((size_t)cells * (size_t)elem_bytes + 15) & ~(size_t)15) + (size_t)cells;
 }
 
-template <bool DISP>
+template <int DISP>
 static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32_t cells, int grid,
                             size_t lds, bool aligned, hipStream_t s)
 {
@@ -427,11 +514,15 @@ static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32
 // reservation, since the footprint has no a-priori bound.
 constexpr Tiling kDispTiling = {3, 3, 4};
 constexpr int32_t kDispLdsCells = 10224;
+static_assert(1 << (3 + 3 + 4 - 2) == kThreads, "one run of a displacement tile per thread");
+static_assert(3 * kDispLdsCells >= 64 * 3 * kProfCtrl * (int32_t)sizeof(float),
+              "the B-spline row profiles of a tile fit its smallest footprint reservation");
 
 hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s)
 {
     FwdJob Js = J0;
-    const Tiling TL = J0.disp ? kDispTiling : TL0;
+    const bool displaced = J0.disp || J0.ctrl;
+    const Tiling TL = displaced ? kDispTiling : TL0;
     Js.tiles_x = (Js.ox + (1 << TL.lx) - 1) >> TL.lx;
     Js.tiles_y = (Js.oy + (1 << TL.ly) - 1) >> TL.ly;
     Js.tiles_z = (Js.oz + (1 << TL.lz) - 1) >> TL.lz;
@@ -441,7 +532,7 @@ hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s
         return hipSuccess;
     const int grid = ((ntiles + 7) >> 3) << 3;
     const int32_t esz = (J.flags & kFlagLds16) ? 2 : 4;
-    const int32_t cells = J.disp ? lds_cells_for(kDispLdsCells, esz)
+    const int32_t cells = displaced ? lds_cells_for(kDispLdsCells, esz)
                                  : lds_cells_for(footprint_cells_bound(J, TL), esz);
     const size_t lds = lds_bytes_for(cells, esz);
     const bool aligned = J.oz % 4 == 0;
@@ -449,10 +540,12 @@ hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s
     Js.sub[0] = SL.lx;
     Js.sub[1] = SL.ly;
     Js.sub[2] = SL.lz;
-    if (J.disp)
-        launch_single_t<true>(Js, TL, ntiles, cells, grid, lds, aligned, s);
+    if (J.ctrl)
+        launch_single_t<kDispSpline>(Js, TL, ntiles, cells, grid, lds, aligned, s);
+    else if (J.disp)
+        launch_single_t<kDispField>(Js, TL, ntiles, cells, grid, lds, aligned, s);
     else
-        launch_single_t<false>(Js, TL, ntiles, cells, grid, lds, aligned, s);
+        launch_single_t<kDispNone>(Js, TL, ntiles, cells, grid, lds, aligned, s);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ def affine_matrix(prm, in_dim, out_dim):
     return np.array(M64[:], dtype=np.float64), np.array(M32[:], dtype=np.float32)
 
 
-def _warp(fn_name, img, M, disp, lbl, fill, label_fill, photo, out_dim, out, lbl_out):
+def _warp(fn_name, img, M, disp, lbl, fill, label_fill, photo, out_dim, out, lbl_out, ctrl=None):
     _require(img, "img", (torch.float32, torch.int16))
     if out_dim is None:
         out_dim = tuple(img.shape) if out is None else tuple(out.shape)
@@ -108,7 +108,15 @@ def _warp(fn_name, img, M, disp, lbl, fill, label_fill, photo, out_dim, out, lbl
     args = [ctypes.byref(vi), _ref(vl), _M32(M)]
     if disp is not None:
         _require(disp, "disp", (torch.float32,), ndim=4)
+        if tuple(disp.shape) != (3,) + tuple(out.shape):
+            raise ValueError(f"disp: expected {(3,) + tuple(out.shape)}, got {tuple(disp.shape)}")
         args.append(ctypes.c_void_p(disp.data_ptr() if disp.numel() else None))
+    if ctrl is not None:
+        _require(ctrl, "ctrl", (torch.float32,), ndim=4)
+        if ctrl.shape[0] != 3:
+            raise ValueError(f"ctrl: expected [3][Gx][Gy][Gz], got {tuple(ctrl.shape)}")
+        args.append(ctypes.c_void_p(ctrl.data_ptr()))
+        args.append((ctypes.c_int64 * 3)(*ctrl.shape[1:]))
     st = getattr(L, fn_name)(*args, float(fill), int(label_fill), _ref(ph), ctypes.byref(vo),
                              _ref(vlo), _stream())
     _lib.check(st, fn_name)
@@ -128,6 +136,15 @@ def warp_displacement(img, M, disp, lbl=None, fill=-1000.0, label_fill=0, photo=
     out_dim = tuple(disp.shape[1:])
     return _warp("ctaug_warp_displacement", img, M, disp, lbl, fill, label_fill, photo, out_dim,
                  out, lbl_out)
+
+
+def warp_bspline(img, M, ctrl, lbl=None, fill=-1000.0, label_fill=0, photo=None, out_dim=None,
+                 out=None, lbl_out=None):
+    """Fused affine + cubic B-spline warp: the displacement of the control grid
+    ctrl [3][Gx][Gy][Gz] is evaluated inside the warp kernel (bitwise equal to
+    bspline_upsample followed by warp_displacement).  Returns (out, lbl_out)."""
+    return _warp("ctaug_warp_bspline", img, M, None, lbl, fill, label_fill, photo, out_dim, out,
+                 lbl_out, ctrl=ctrl)
 
 
 def photometric_noise(volume, photo):
@@ -190,6 +207,8 @@ def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp):
         _lib.check(st, "ctaug_warp_affine_backward")
         return g_img, g_M
     _require(disp, "disp", (torch.float32,), ndim=4)
+    if tuple(disp.shape) != (3,) + tuple(grad_out.shape):
+        raise ValueError(f"disp: expected {(3,) + tuple(grad_out.shape)}, got {tuple(disp.shape)}")
     g_disp = torch.empty_like(disp) if want_disp else None
     st = L.ctaug_warp_displacement_backward(ctypes.byref(vi), _M32(M), p(disp), float(fill),
                                             ctypes.byref(vg), _ref(vgi), p(g_M), p(g_disp), p(ws),

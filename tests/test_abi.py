@@ -265,6 +265,27 @@ def test_bspline_validation(L):
     assert L.ctaug_bspline_upsample_adjoint(FAKE, od, g, None, FAKE, need, None) == EINVAL
 
 
+def test_fused_bspline_warp_validation(L):
+    r = ctypes.byref
+    img, out = vol((8, 8, 8), I16), vol((32, 32, 32))
+    g = (ctypes.c_int64 * 3)(8, 8, 8)
+
+    def call(ctrl, G, out_vol=out, M=None):
+        return L.ctaug_warp_bspline(r(img), None, mat() if M is None else M, ctrl, G, 0.0, 0,
+                                    None, r(out_vol), None, None)
+
+    assert call(None, g) == EINVAL                 # no control grid
+    assert call(FAKE, None) == EINVAL              # no grid dims
+    for G in [(3, 8, 8), (8, 65, 8), (8, 8, 0)]:
+        assert call(FAKE, (ctypes.c_int64 * 3)(*G)) == ESHAPE
+    bad = mat()
+    bad[3] = float("nan")
+    assert call(FAKE, g, M=bad) == EINVAL
+    assert call(FAKE, g, out_vol=vol((32, 32, 32), I16)) == EDTYPE
+    # an empty output needs no control grid and touches nothing
+    assert call(None, g, out_vol=vol((0, 32, 32), data=None)) == OK
+
+
 # -- batch plan ---------------------------------------------------------------
 
 def _job(in_dims=(8, 8, 8), out_dims=(4, 4, 4), dtype=I16):

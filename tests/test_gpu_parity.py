@@ -369,6 +369,92 @@ def test_bspline_adjoint_parity(out_dim, grid):
     assert_grad(_np(gc), ref, "g_ctrl")
 
 
+def _smooth_volume(dims, seed):
+    """Seeded smooth HU volume (sums of low-frequency sinusoids, |grad| below
+    about 400 HU per voxel)."""
+    rng = np.random.default_rng(seed)
+    x, y, z = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in dims], indexing="ij")
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    v = (300.0 * np.sin(2 * np.pi * x / 23 + ph[0]) * np.cos(2 * np.pi * y / 19 + ph[1])
+         + 250.0 * np.sin(2 * np.pi * z / 17 + ph[2]) - 200.0)
+    return v.astype(np.float32)
+
+
+def _assert_labels_up_to_ties(got, ref, lbl, M, u64, label_fill=0, eps=1e-3):
+    """Nearest-neighbour labels of a warp whose displacement the two sides
+    round differently: equal wherever q + 0.5 is farther than eps from an
+    integer on every axis; elsewhere the label of one of the candidate voxels."""
+    od = got.shape
+    p = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in od], indexing="ij"))
+    A = np.asarray(M, np.float64).reshape(3, 4)
+    q = np.einsum("ij,jxyz->ixyz", A[:, :3], p) + A[:, 3][:, None, None, None] + u64
+    r = q + 0.5
+    tie = np.abs(r - np.round(r)) < eps
+    amb = tie.any(axis=0)
+    assert np.array_equal(got[~amb], ref[~amb])
+    assert amb.mean() < 0.02
+    n = lbl.shape
+    for idx in zip(*np.nonzero(amb & (got != ref))):
+        cands = []
+        for i in range(3):
+            j = int(np.floor(r[(i,) + idx]))
+            cands.append({j, j - 1, j + 1} if tie[(i,) + idx] else {j})
+        ok = set()
+        for jx in cands[0]:
+            for jy in cands[1]:
+                for jz in cands[2]:
+                    inside = 0 <= jx < n[0] and 0 <= jy < n[1] and 0 <= jz < n[2]
+                    ok.add(int(lbl[jx, jy, jz]) if inside else label_fill)
+        assert int(got[idx]) in ok, (idx, got[idx], ok)
+
+
+@pytest.mark.parametrize("in_dim,out_dim,grid,dtype,amp", [
+    ((40, 36, 28), (38, 34, 24), (8, 8, 8), np.float32, 3.0),
+    ((40, 36, 28), (30, 26, 21), (6, 5, 7), np.int16, 6.0),      # ragged z, unaligned runs
+    ((24, 20, 60), (20, 18, 52), (5, 6, 40), np.float32, 1.5),   # controls < 4 voxels apart
+    ((33, 30, 18), (33, 30, 1), (4, 4, 4), np.int16, 2.0),       # single slice
+])
+def test_warp_bspline_equals_upsample_then_warp(in_dim, out_dim, grid, dtype, amp):
+    """The fused nonrigid warp evaluates the B-spline field with the upsampling
+    kernel's operations in the same order: bit-identical to upsampling the
+    field and warping with it, labels and noise included."""
+    rng = np.random.default_rng(sum(out_dim) + grid[2])
+    img, lbl = phantom_pair(in_dim, seed=91)
+    prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    C = (amp * rng.standard_normal((3,) + grid)).astype(np.float32)
+    ph = draw_photo(rng, AugmentRanges(), seed=5, volume_id=2)
+    ti, tl, tc = _t(img.astype(dtype)), _t(lbl), _t(C)
+    out, lout = ctaug.warp_bspline(ti, M, tc, lbl=tl, photo=ph, out_dim=out_dim)
+    u = ctaug.bspline_upsample(tc, out_dim)
+    out2, lout2 = ctaug.warp_displacement(ti, M, u, lbl=tl, photo=ph)
+    assert np.array_equal(_np(out).view(np.uint32), _np(out2).view(np.uint32))
+    assert np.array_equal(_np(lout), _np(lout2))
+
+
+@pytest.mark.parametrize("out_dim,grid,windowed", [((44, 40, 36), (8, 8, 8), True),
+                                                   ((37, 29, 23), (6, 7, 5), False)])
+def test_warp_bspline_parity_with_oracle_chain(out_dim, grid, windowed):
+    """Fused nonrigid warp against the oracle's own chain (FP64 B-spline field
+    rounded to FP32, then the warp).  The two fields differ by FP32 rounding of
+    the spline sum, so intensities are compared on a smooth volume (the error
+    |grad I| |du| stays far below the bar) and labels up to rounding ties."""
+    in_dim = (48, 44, 40)
+    rng = np.random.default_rng(61 + grid[0])
+    img = _smooth_volume(in_dim, seed=3)
+    _, lbl = phantom_pair(in_dim, seed=8)
+    prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    C = (4.0 * rng.standard_normal((3,) + grid)).astype(np.float32)
+    rg = AugmentRanges(window=windowed)
+    ph = draw_photo(rng, rg, seed=17, volume_id=4)
+    out, lout = ctaug.warp_bspline(_t(img), M, _t(C), lbl=_t(lbl), photo=ph, out_dim=out_dim)
+    u64 = oracle.bspline_upsample(C, out_dim)
+    ref, lref = oracle.warp(img, M, out_dim, lbl=lbl, disp=u64.astype(np.float32), photo=ph)
+    assert_intensity(_np(out), ref, windowed=windowed, what="fused B-spline warp")
+    _assert_labels_up_to_ties(_np(lout), lref, lbl, M, u64)
+
+
 # ---------------------------------------------------------------------------
 # Backward
 # ---------------------------------------------------------------------------
@@ -489,12 +575,20 @@ def test_autograd_affine_and_nonrigid_chain():
     assert_grad(M.grad.numpy(), r_M, "autograd g_M")
 
     ctrl = rng.normal(0.0, 2.0, (3, 6, 6, 6)).astype(np.float32)
+    # the oracle's own field; the upstream gradient is zeroed where a sample
+    # lies within 1e-3 of a cell boundary, where dV/dq jumps and the two FP32
+    # roundings of u could select different cells
+    u64 = oracle.bspline_upsample(ctrl, dims)
+    p = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in dims], indexing="ij"))
+    A = M32.astype(np.float64).reshape(3, 4)
+    q = np.einsum("ij,jxyz->ixyz", A[:, :3], p) + A[:, 3][:, None, None, None] + u64
+    g2 = np.where((np.abs(q - np.round(q)) < 1e-3).any(axis=0), 0.0, g).astype(np.float32)
     c = _t(ctrl).requires_grad_(True)
     u = ag.bspline_upsample(c, dims)
     out2 = ag.warp_displacement(_t(img_np), torch.tensor(M32.astype(np.float64)), u)
-    (out2 * _t(g)).sum().backward()
-    _, _, r_u = oracle.warp_backward(img_np, M32, g, disp=_np(u), want_img=False, want_M=False,
-                                     want_u=True)
+    (out2 * _t(g2)).sum().backward()
+    _, _, r_u = oracle.warp_backward(img_np, M32, g2, disp=u64.astype(np.float32), want_img=False,
+                                     want_M=False, want_u=True)
     assert_grad(_np(c.grad), oracle.bspline_adjoint(r_u, (6, 6, 6)), "autograd g_ctrl")
 
 
@@ -526,7 +620,7 @@ def test_resampling_pipeline_parity():
     _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
     out, lout = ctaug.warp_affine(sm, M, lbl=_t(lbl), out_dim=out_dim)
     ref_sm = oracle.gaussian_smooth(img, np.asarray(sig, dtype=np.float64))
-    ref, lref = oracle.warp(_np(sm), M, out_dim, lbl=lbl)
+    ref, lref = oracle.warp(ref_sm, M, out_dim, lbl=lbl)
     assert_intensity(_np(sm), ref_sm, windowed=False, what="smoothed")
     assert_intensity(_np(out), ref, windowed=False, what="resampled")
     assert np.array_equal(_np(lout), lref)
