@@ -264,6 +264,28 @@ ctaug_status ctaug_warp_bspline(const ctaug_vol *img_in, const ctaug_vol *lbl_in
                                 float fill, int32_t label_fill, const ctaug_photo *photo,
                                 ctaug_vol *img_out, ctaug_vol *lbl_out, void *stream);
 
+/* Workspace bytes for ctaug_warp_bspline_backward (0 on bad arguments). */
+size_t ctaug_warp_bspline_backward_workspace(const int64_t out_dim[3], const int64_t G[3]);
+
+/* Adjoint of ctaug_warp_bspline's image path: grad_img and grad_M as in
+ * ctaug_warp_affine_backward (q now includes the spline displacement), and
+ *   grad_ctrl = B^T grad_disp,  grad_disp[i](p) = grad_out(p) dV/dq_i(p)
+ * (device float [3][Gx][Gy][Gz], overwritten, or NULL): the gradient with
+ * respect to the control grid, without a dense field in memory when the
+ * grid has at most 2048 entries and no 8 x 8 x 16 output tile touches more
+ * than 8 controls along an axis (otherwise grad_disp is staged in the
+ * workspace and contracted by the B-spline adjoint).  Reduced in FP64 in a
+ * fixed order (deterministic).  ws: device workspace of at least
+ * ctaug_warp_bspline_backward_workspace(grad_out dims, G) bytes, required
+ * when grad_M or grad_ctrl is given.
+ * Errors: EINVAL (null required pointer, non-finite M or fill), EDTYPE,
+ * ESHAPE (dims mismatch, bad grid), EWORKSPACE, EHIP. */
+ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, const float M[12],
+                                         const float *ctrl, const int64_t G[3], float fill,
+                                         const ctaug_vol *grad_out, ctaug_vol *grad_img,
+                                         double *grad_M, float *grad_ctrl, void *ws,
+                                         size_t ws_bytes, void *stream);
+
 /* Workspace bytes for ctaug_bspline_upsample_adjoint. */
 size_t ctaug_bspline_adjoint_workspace(const int64_t out_dim[3], const int64_t G[3]);
 

@@ -69,6 +69,8 @@ def _declare(L):
     L.orc_warp_backward.restype = _int
     L.orc_bspline_upsample.argtypes = [_p, _p, _p, _p]
     L.orc_bspline_upsample.restype = _int
+    L.orc_bspline_upsample_f32.argtypes = [_p, _p, _p, _p]
+    L.orc_bspline_upsample_f32.restype = _int
     L.orc_bspline_adjoint.argtypes = [_p, _p, _p, _p]
     L.orc_bspline_adjoint.restype = _int
     L.orc_resample_sigma.argtypes = [_p, _dbl, _p]
@@ -217,6 +219,16 @@ def bspline_upsample(ctrl, out_dim):
     od = _dims(out_dim)
     u = np.empty((3,) + tuple(od), dtype=np.float64)
     _check(lib().orc_bspline_upsample(_ptr(c), _ptr(G), _ptr(od), _ptr(u)))
+    return u
+
+
+def bspline_upsample_f32(ctrl, out_dim):
+    """Parity-mode field (float32, roundings fixed as the fused warp's)."""
+    c = _c(ctrl, np.float32)
+    G = _dims(c.shape[1:])
+    od = _dims(out_dim)
+    u = np.empty((3,) + tuple(int(v) for v in out_dim), dtype=np.float32)
+    _check(lib().orc_bspline_upsample_f32(_ptr(c), _ptr(G), _ptr(od), _ptr(u)))
     return u
 
 

@@ -9,10 +9,12 @@
  * obviously correct reading of the paper.  It shares no code, header, table
  * or constant with the GPU library.
  *
- * Arithmetic: FP64 everywhere, except for two expressions that the GPU must
+ * Arithmetic: FP64 everywhere, except for expressions that the GPU must
  * reproduce bit for bit and which are therefore pinned to FP32 here as well:
- *   - the sampling coordinate q = A x + b (one fmaf chain per axis), and
- *   - the nearest-neighbour label rounding floorf(q + 0.5f).
+ *   - the sampling coordinate q = A x + b (one fmaf chain per axis),
+ *   - the nearest-neighbour label rounding floorf(q + 0.5f), and
+ *   - the parity-mode B-spline field of warps that evaluate it themselves
+ *     (orc_bspline_upsample_f32; the FP64 field is orc_bspline_upsample).
  * "exact" mode replaces the pinned FP32 coordinate with FP64 and is used only
  * to validate gradient formulas by finite differences.
  *
@@ -544,6 +546,73 @@ int orc_bspline_upsample(const double *ctrl, const int64_t *G, const int64_t *ou
                             for (int c = 0; c < 4; ++c)
                                 s += Bx[a] * By[b] * Bz[c] *
                                      ctrl[comp * GN + ((ix + a) * G[1] + (iy + b)) * G[2] + (iz + c)];
+                    u[comp * N + v] = s;
+                }
+            }
+    return ORC_OK;
+}
+
+/* Parity mode of the field, for warps that evaluate it themselves: the same
+ * definition in FP32 with every rounding fixed, so that a kernel that follows
+ * the same steps agrees bit for bit (as the pinned coordinate map does).
+ * Per axis: inv_h = (float)((G - 3) / (n - 1)) (0 when n = 1); s = (float)p *
+ * inv_h; i = min(floor(s), G - 4); t = s - i.  Basis with m = 1 - t, t2 = t*t,
+ * t3 = t2*t, k = 1/6 rounded to FP32: B0 = ((m*m)*m)*k, B1 = fmaf(3, t3,
+ * fmaf(-6, t2, 4))*k, B2 = fmaf(-3, t3, fmaf(3, t2, fmaf(3, t, 1)))*k,
+ * B3 = t3*k.  Sums: P(gz) = sum_a Bx_a (sum_b By_b C[ix+a][iy+b][gz]) and
+ * u = sum_c Bz_c P(iz+c), each a chain of fmaf from 0 in index order. */
+static void bspline_cell_f32(int64_t p, int64_t n, int64_t G, int64_t *i, float *t)
+{
+    const float inv_h = n > 1 ? (float)((double)(G - 3) / (double)(n - 1)) : 0.0f;
+    const float s = (float)p * inv_h;
+    const float f = fminf(floorf(s), (float)(G - 4));
+    *i = (int64_t)f;
+    *t = s - f;
+}
+
+static void bspline_basis_f32(float t, float B[4])
+{
+    const float t2 = t * t, t3 = t2 * t, m = 1.0f - t, k = 1.0f / 6.0f;
+    B[0] = m * m * m * k;
+    B[1] = fmaf(3.0f, t3, fmaf(-6.0f, t2, 4.0f)) * k;
+    B[2] = fmaf(-3.0f, t3, fmaf(3.0f, t2, fmaf(3.0f, t, 1.0f))) * k;
+    B[3] = t3 * k;
+}
+
+int orc_bspline_upsample_f32(const float *ctrl, const int64_t *G, const int64_t *out_dim, float *u)
+{
+    if (!ctrl || !u || !dims_ok(out_dim) || !G || G[0] < 4 || G[1] < 4 || G[2] < 4)
+        return ORC_EINVAL;
+    const int64_t X = out_dim[0], Y = out_dim[1], Z = out_dim[2], N = X * Y * Z;
+    const int64_t GN = G[0] * G[1] * G[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < X; ++x)
+        for (int64_t y = 0; y < Y; ++y)
+            for (int64_t z = 0; z < Z; ++z) {
+                int64_t ix, iy, iz;
+                float tx, ty, tz, Bx[4], By[4], Bz[4];
+                bspline_cell_f32(x, X, G[0], &ix, &tx);
+                bspline_cell_f32(y, Y, G[1], &iy, &ty);
+                bspline_cell_f32(z, Z, G[2], &iz, &tz);
+                bspline_basis_f32(tx, Bx);
+                bspline_basis_f32(ty, By);
+                bspline_basis_f32(tz, Bz);
+                const int64_t v = (x * Y + y) * Z + z;
+                for (int comp = 0; comp < 3; ++comp) {
+                    float s = 0.0f;
+                    for (int c = 0; c < 4; ++c) {
+                        float P = 0.0f;
+                        for (int a = 0; a < 4; ++a) {
+                            float sa = 0.0f;
+                            for (int b = 0; b < 4; ++b)
+                                sa = fmaf(By[b],
+                                          ctrl[comp * GN + ((ix + a) * G[1] + (iy + b)) * G[2] +
+                                               (iz + c)],
+                                          sa);
+                            P = fmaf(Bx[a], sa, P);
+                        }
+                        s = fmaf(Bz[c], P, s);
+                    }
                     u[comp * N + v] = s;
                 }
             }

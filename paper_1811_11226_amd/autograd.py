@@ -59,6 +59,30 @@ class WarpDisplacementFn(torch.autograd.Function):
         return g_img, g_M, g_disp, None
 
 
+class WarpBsplineFn(torch.autograd.Function):
+    """out = warp(img; M, B ctrl) with the B-spline displacement evaluated in
+    the warp kernel; gradients to img, M and the control grid ctrl."""
+
+    @staticmethod
+    def forward(ctx, img, M, ctrl, fill=-1000.0, out_dim=None):
+        Mh = _m_host(M)
+        out, _ = ops.warp_bspline(img, Mh, ctrl.contiguous(), fill=fill, out_dim=out_dim)
+        ctx.save_for_backward(img, ctrl)
+        ctx.Mh, ctx.fill, ctx.M_meta = Mh, fill, (M.device, M.dtype)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        img, ctrl = ctx.saved_tensors
+        g_img, g_M, g_ctrl = ops.warp_bspline_backward(
+            img, ctx.Mh, ctrl.contiguous(), grad_out.contiguous(), fill=ctx.fill,
+            want_img=ctx.needs_input_grad[0], want_M=ctx.needs_input_grad[1],
+            want_ctrl=ctx.needs_input_grad[2])
+        if g_M is not None:
+            g_M = g_M.to(ctx.M_meta[0], ctx.M_meta[1])
+        return g_img, g_M, g_ctrl, None, None
+
+
 class BSplineUpsampleFn(torch.autograd.Function):
     """disp = B ctrl (cubic B-spline upsampling) with gradient B^T g."""
 
@@ -78,6 +102,10 @@ def warp_affine(img, M, fill=-1000.0, out_dim=None):
 
 def warp_displacement(img, M, disp, fill=-1000.0):
     return WarpDisplacementFn.apply(img, M, disp, fill)
+
+
+def warp_bspline(img, M, ctrl, fill=-1000.0, out_dim=None):
+    return WarpBsplineFn.apply(img, M, ctrl, fill, out_dim)
 
 
 def bspline_upsample(ctrl, out_dim):

@@ -471,7 +471,8 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
     return hip_status(launch_warp_bwd(J, static_cast<const float *>(grad_out->data),
                                       grad_img ? static_cast<float *>(grad_img->data) : nullptr,
                                       need_disp ? grad_disp : nullptr, grad_M,
-                                      static_cast<double *>(ws), as_stream(stream)));
+                                      static_cast<double *>(ws), nullptr, nullptr,
+                                      as_stream(stream)));
 }
 
 extern "C" ctaug_status ctaug_warp_affine_backward(const ctaug_vol *img_in, const float M[12],
@@ -492,6 +493,99 @@ extern "C" ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in
 {
     return backward_impl(img_in, M, disp, true, fill, grad_out, grad_img, grad_M, grad_disp, ws,
                          ws_bytes, stream);
+}
+
+// Workspace of ctaug_warp_bspline_backward: grad_M partials, then either the
+// per-workgroup control-grid rows (fused adjoint) or, for grids the fused
+// kernel does not take, the dense field, its gradient and the B-spline
+// adjoint's workspace.
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+extern "C" size_t ctaug_warp_bspline_backward_workspace(const int64_t out_dim[3],
+                                                        const int64_t G[3])
+{
+    if (!out_dim || !dims_valid(out_dim) || !grid_valid(G))
+        return 0;
+    const int64_t rows = bwd_partial_rows(out_dim[0], out_dim[1], out_dim[2]);
+    const size_t m = align256((size_t)rows * 12 * sizeof(double));
+    const BsplineGeom B = bspline_geom(G, out_dim);
+    if (bwd_ctrl_fused(B))
+        return m + (size_t)rows * 3 * G[0] * G[1] * G[2] * sizeof(double);
+    const size_t field = align256((size_t)(3 * nelem(out_dim)) * sizeof(float));
+    return m + 2 * field + (size_t)bspline_adj_ws_bytes(out_dim, G);
+}
+
+extern "C" ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, const float M[12],
+                                                    const float *ctrl, const int64_t G[3],
+                                                    float fill, const ctaug_vol *grad_out,
+                                                    ctaug_vol *grad_img, double *grad_M,
+                                                    float *grad_ctrl, void *ws, size_t ws_bytes,
+                                                    void *stream)
+{
+    ctaug_status st;
+    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+        return st;
+    if ((st = check_vol(grad_out, 1u << CTAUG_F32)) != CTAUG_OK)
+        return st;
+    if (grad_img) {
+        if ((st = check_vol(grad_img, 1u << CTAUG_F32)) != CTAUG_OK)
+            return st;
+        if (!same_dims(grad_img, img_in))
+            return CTAUG_ESHAPE;
+    }
+    if (!G)
+        return CTAUG_EINVAL;
+    if (!grid_valid(G))
+        return CTAUG_ESHAPE;
+    const int64_t *od = grad_out->dim;
+    const BsplineGeom B = bspline_geom(G, od);
+    // fused kernel (field evaluated in the adjoint), or the dense route
+    const bool fused = grad_ctrl ? bwd_ctrl_fused(B) : bwd_spline_eval_ok(B);
+    if (!fused && 3 * nelem(od) > kMaxElems)
+        return CTAUG_ESHAPE;
+    const size_t need = ctaug_warp_bspline_backward_workspace(od, G);
+    if ((grad_M || grad_ctrl || !fused) && need > 0 && (!ws || ws_bytes < need))
+        return CTAUG_EWORKSPACE;
+    FwdJob J;
+    ctaug_vol out_like = *grad_out;    // the gradient plays the part of the output (dims only)
+    st = make_job(img_in, nullptr, M, nullptr, false, fill, 0, nullptr, &out_like, nullptr,
+                  kDefaultTiling, J);
+    if (st != CTAUG_OK)
+        return st;
+    J.out = nullptr;
+    if (!empty(J) && !ctrl)
+        return CTAUG_EINVAL;
+    if (empty(J) && !grad_M && !grad_ctrl)
+        return CTAUG_OK;
+    const float *g = static_cast<const float *>(grad_out->data);
+    float *gi = grad_img ? static_cast<float *>(grad_img->data) : nullptr;
+    char *w = static_cast<char *>(ws);
+    double *partials = reinterpret_cast<double *>(w);
+    const size_t m = align256((size_t)bwd_partial_rows(od[0], od[1], od[2]) * 12 * sizeof(double));
+    hipStream_t s = as_stream(stream);
+    if (fused) {
+        J.ctrl = ctrl;
+        J.bs = B;
+        return hip_status(launch_warp_bwd(J, g, gi, nullptr, grad_M, partials,
+                                          grad_ctrl ? reinterpret_cast<double *>(w + m) : nullptr,
+                                          grad_ctrl, s));
+    }
+    // dense route: u = upsample(ctrl), adjoint with g_disp, then B^T g_disp
+    const size_t field = align256((size_t)(3 * nelem(od)) * sizeof(float));
+    float *u = reinterpret_cast<float *>(w + m);
+    float *g_disp = reinterpret_cast<float *>(w + m + field);
+    double *adj_ws = reinterpret_cast<double *>(w + m + 2 * field);
+    if (!empty(J)) {
+        const bool vec = od[2] % 4 == 0;   // workspace offsets are 256-byte aligned
+        if ((st = hip_status(launch_bspline_up(ctrl, G, od, u, vec, s))) != CTAUG_OK)
+            return st;
+        J.disp = u;
+    }
+    st = hip_status(launch_warp_bwd(J, g, gi, grad_ctrl ? g_disp : nullptr, grad_M, partials,
+                                    nullptr, nullptr, s));
+    if (st != CTAUG_OK || !grad_ctrl)
+        return st;
+    return hip_status(launch_bspline_adj(g_disp, od, G, grad_ctrl, adj_ws, s));
 }
 
 extern "C" ctaug_status ctaug_bspline_upsample(const float *ctrl, const int64_t G[3],

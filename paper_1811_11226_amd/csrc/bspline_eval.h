@@ -73,6 +73,78 @@ __device__ __forceinline__ float bs_profile(const float *__restrict__ ctrl, cons
     return s;
 }
 
+// Displacement of one thread's run of a tile of 2^lx x 2^ly rows (x, y) by
+// 2^lz voxels along z, evaluated from the control grid: the row profiles of
+// the tile's rows over its z-control window are computed into s_prof (LDS,
+// 2^(lx+ly) * 3 * kSplineWindow floats), then each thread contracts z for its
+// own voxels z .. z + nvalid - 1 of row rr (x = x0 + (rr >> ly), y = y0 +
+// (rr & (2^ly - 1))).  A window of more than kSplineWindow controls (controls
+// closer than about 4 voxels along z) evaluates the profiles per voxel when
+// PER_VOXEL is set; without it the caller guarantees that every window fits.
+// Contains a workgroup barrier: every thread of the workgroup calls it.
+constexpr int kSplineWindow = 8;
+
+template <int NT, bool PER_VOXEL = true>
+__device__ __forceinline__ void spline_tile_u(const float *__restrict__ ctrl, const BsplineGeom &B,
+                                              int lx, int ly, int x0, int y0, int z0, int x1,
+                                              int y1, int z1, int rr, int x, int y, int z,
+                                              int nvalid, bool mine, float *s_prof,
+                                              float (&u)[3][4])
+{
+    const int izl = bs_index(z0, B.inv_hz, B.gz);
+    const int ncz = bs_index(z1, B.inv_hz, B.gz) - izl + 4;
+    if (!PER_VOXEL || ncz <= kSplineWindow) {
+        const int per_row = 3 * ncz;
+        const int nent = per_row << (lx + ly);
+        for (int e = threadIdx.x; e < nent; e += NT) {
+            const int row = e / per_row;
+            const int rem = e - row * per_row;
+            const int comp = rem / ncz, c = rem - comp * ncz;
+            const int px = min(x0 + (row >> ly), x1);
+            const int py = min(y0 + (row & ((1 << ly) - 1)), y1);
+            s_prof[e] = bs_profile(ctrl, B, comp, px, py, izl + c);
+        }
+        __syncthreads();
+        if (!mine)
+            return;
+        const float *P = s_prof + rr * per_row - izl;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= nvalid)
+                break;
+            int32_t iz;
+            float tz, Bz[4];
+            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
+            bs_basis(tz, Bz);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                float s = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    s = __builtin_fmaf(Bz[c], P[comp * ncz + iz + c], s);
+                u[comp][k] = s;
+            }
+        }
+    } else if (PER_VOXEL && mine) {
+        for (int k = 0; k < nvalid; ++k) {
+            int32_t iz;
+            float tz, Bz[4];
+            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
+            bs_basis(tz, Bz);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                float s = 0.0f;
+#pragma unroll 1
+                for (int c = 0; c < 4; ++c) {
+                    const float bz = c == 0 ? Bz[0] : c == 1 ? Bz[1] : c == 2 ? Bz[2] : Bz[3];
+                    s = __builtin_fmaf(bz, bs_profile(ctrl, B, comp, x, y, iz + c), s);
+                }
+                u[comp][k] = s;
+            }
+        }
+    }
+}
+
 // Host: geometry of a control grid G over output dims od.
 inline BsplineGeom bspline_geom(const int64_t G[3], const int64_t od[3])
 {

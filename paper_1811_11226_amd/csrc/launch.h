@@ -33,8 +33,16 @@ hipError_t launch_box_muller(const uint32_t *words, int64_t npairs, float *out, 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 int64_t bwd_partial_rows(int64_t ox, int64_t oy, int64_t oz);
+// Adjoint of a warp.  A control grid (J.ctrl) requires bwd_spline_eval_ok(J.bs)
+// (every tile's z window of controls fits the kernel's row profiles); its
+// gradient g_ctrl is fused into the adjoint when bwd_ctrl_fused(J.bs) holds,
+// with ctrl_part holding bwd_partial_rows() rows of 3 Gx Gy Gz doubles.
+// Otherwise the caller materialises the field and uses the dense path.
 hipError_t launch_warp_bwd(const FwdJob &J, const float *g, float *g_img, float *g_disp,
-                           double *g_M, double *partials, hipStream_t s);
+                           double *g_M, double *partials, double *ctrl_part, float *g_ctrl,
+                           hipStream_t s);
+bool bwd_spline_eval_ok(const BsplineGeom &B);
+bool bwd_ctrl_fused(const BsplineGeom &B);
 
 int bspline_max_grid();
 int64_t bspline_adj_ws_bytes(const int64_t od[3], const int64_t G[3]);

@@ -10,6 +10,13 @@
 //                                   displacement warps (no footprint bound):
 //                                   global FP32 atomics per corner
 //   grad_disp[i](p) = g * dV/dq_i   coalesced SoA stores
+//   grad_ctrl                        B-spline warps evaluated from a control
+//                                   grid: the tile's g dV/dq is contracted
+//                                   with the spline weights along z, y and x
+//                                   in LDS and added to FP64 accumulators that
+//                                   each thread keeps for its own control
+//                                   entries; one row per workgroup, summed by
+//                                   a second kernel in a fixed order
 //   per-tile partial of grad_M[i][j] = sum g dV/dq_i [x,y,z,1]_j, reduced in
 //   FP64 inside the workgroup in a fixed order and written to workspace slot
 //   (tile); a second kernel sums the slots in a fixed order.  grad_M is
@@ -20,6 +27,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 
 namespace ctaug {
 
@@ -69,11 +77,135 @@ __device__ __forceinline__ void cell_gradient(const float K[8], const float tt[3
                  tt[0]);
 }
 
-template <typename T, bool DISP>
+// Largest control grid (3 Gx Gy Gz entries) whose gradient is fused into the
+// adjoint kernel: one FP64 row per workgroup in the workspace.
+constexpr int32_t kCtrlMaxEntries = 2048;
+
+// Spline weight matrix of one tile axis: Wt[p][c] = B_{c - (i(p) - i(p0))}(t(p))
+// for the 2^lp voxels p0 + p <= p1 of the axis and the window of kSplineWindow
+// controls starting at i(p0); 0 elsewhere.  One entry per calling thread.
+__device__ __forceinline__ void spline_weight_entry(int e, int p0, int p1, float inv_h, int32_t G,
+                                                    float *Wt)
+{
+    const int p = p0 + (e / kSplineWindow), c = e % kSplineWindow;
+    float w = 0.0f;
+    if (p <= p1) {
+        int32_t i;
+        float t, Bw[4];
+        bs_cell(p, inv_h, G, i, t);
+        bs_basis(t, Bw);
+        const int j = c - (i - bs_index(p0, inv_h, G));
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+            if (j == jj)
+                w = Bw[jj];
+    }
+    Wt[e] = w;
+}
+
+// Control-grid adjoint of one 8 x 8 x 16 displacement tile.  gu[k][i] is
+// g dV/dq_i of voxel k of the thread's run (0 outside the tile or the guard).
+// Contractions in LDS, each in a fixed order (FP32 inside the tile):
+//   W[row][i][c]   = sum_z  Zw[z][c] gu_i(row, z)        (4 lanes of a row, butterfly)
+//   H[x][i][b][c]  = sum_y  Yw[y][b] W[(x, y)][i][c]
+//   R[i][a][b][c]  = sum_x  Xw[x][a] H[x][i][b][c]
+// then R is added to the workgroup's FP64 row of the workspace (each entry of
+// the row is updated by one thread per tile, tiles in a fixed order, so the
+// row is deterministic).  Every axis window must hold at most kSplineWindow
+// controls (checked on the host).  The caller guarantees that no thread reads
+// LDS on entry; ends with a barrier, which also orders the row updates of
+// consecutive tiles.
+__device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, int y0, int z0,
+                                                  int x1, int y1, int z1, int rr, int zr,
+                                                  const float (&gu)[4][3], float *lds,
+                                                  double *__restrict__ row)
+{
+    constexpr int NW = kSplineWindow;
+    static_assert(NW == 8, "window entries are indexed with 3-bit fields");
+    float *Zw = lds;                           // [16][NW]
+    float *Yw = Zw + 16 * NW;                  // [8][NW]
+    float *Xw = Yw + 8 * NW;                   // [8][NW]
+    float *W = Xw + 8 * NW;                    // [64][3][NW]
+    float *H = W + 64 * 3 * NW;                // [8][3][NW][NW]
+    float *R = H + 8 * 3 * NW * NW;            // [3][NW][NW][NW]
+    const int t = threadIdx.x;
+    if (t < 16 * NW)
+        spline_weight_entry(t, z0, z1, B.inv_hz, B.gz, Zw);
+    else if (t < 24 * NW)
+        spline_weight_entry(t - 16 * NW, y0, y1, B.inv_hy, B.gy, Yw);
+    else if (t < 32 * NW)
+        spline_weight_entry(t - 24 * NW, x0, x1, B.inv_hx, B.gx, Xw);
+    __syncthreads();
+    // z: the 4 lanes of a row hold its 16 voxels; butterfly sum over them
+#pragma unroll 1
+    for (int c = 0; c < NW; ++c) {
+        const float *zc = Zw + (4 * zr) * NW + c;
+        const float w0 = zc[0], w1 = zc[NW], w2 = zc[2 * NW], w3 = zc[3 * NW];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float v = w0 * gu[0][i];
+            v = __builtin_fmaf(w1, gu[1][i], v);
+            v = __builtin_fmaf(w2, gu[2][i], v);
+            v = __builtin_fmaf(w3, gu[3][i], v);
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            if (zr == 0)
+                W[(rr * 3 + i) * NW + c] = v;
+        }
+    }
+    __syncthreads();
+    if (t < 8 * 3 * NW) {                      // (x, i, c) -> H[x][i][b][c] for every b
+        const int xr = t / (3 * NW), ic = t - xr * 3 * NW;
+        const int i = ic / NW, c = ic - i * NW;
+        float wv[8];
+#pragma unroll
+        for (int yr = 0; yr < 8; ++yr)
+            wv[yr] = W[((xr * 8 + yr) * 3 + i) * NW + c];
+#pragma unroll 1
+        for (int b = 0; b < NW; ++b) {
+            float h = 0.0f;
+#pragma unroll
+            for (int yr = 0; yr < 8; ++yr)
+                h = __builtin_fmaf(Yw[yr * NW + b], wv[yr], h);
+            H[((xr * 3 + i) * NW + b) * NW + c] = h;
+        }
+    }
+    __syncthreads();
+    if (t < 3 * NW * NW) {                     // (i, b, c) -> R[i][a][b][c] for every a
+        const int i = t / (NW * NW), bc = t - i * NW * NW;
+        float hv[8];
+#pragma unroll
+        for (int xr = 0; xr < 8; ++xr)
+            hv[xr] = H[(xr * 3 + i) * NW * NW + bc];
+#pragma unroll 1
+        for (int a = 0; a < NW; ++a) {
+            float r = 0.0f;
+#pragma unroll
+            for (int xr = 0; xr < 8; ++xr)
+                r = __builtin_fmaf(Xw[xr * NW + a], hv[xr], r);
+            R[(i * NW + a) * NW * NW + bc] = r;
+        }
+    }
+    __syncthreads();
+    const int ixl = bs_index(x0, B.inv_hx, B.gx), iyl = bs_index(y0, B.inv_hy, B.gy),
+              izl = bs_index(z0, B.inv_hz, B.gz);
+    const int ncx = bs_index(x1, B.inv_hx, B.gx) - ixl + 4,
+              ncy = bs_index(y1, B.inv_hy, B.gy) - iyl + 4,
+              ncz = bs_index(z1, B.inv_hz, B.gz) - izl + 4;
+    for (int e = t; e < 3 * NW * NW * NW; e += kThreads) {
+        const int c = e & (NW - 1), b = (e >> 3) & (NW - 1), a = (e >> 6) & (NW - 1), i = e >> 9;
+        if (a < ncx && b < ncy && c < ncz)
+            row[((i * B.gx + ixl + a) * B.gy + iyl + b) * B.gz + izl + c] += (double)R[e];
+    }
+    __syncthreads();
+}
+
+template <typename T, int DISP>
 __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__restrict__ g,
                                                        float *__restrict__ g_img,
                                                        float *__restrict__ g_disp,
                                                        double *__restrict__ partials,
+                                                       double *__restrict__ ctrl_part,
                                                        int32_t ntiles, int32_t lds_cells)
 {
     const Tiling TL = kBwdTiling;
@@ -91,6 +223,16 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
 #pragma unroll
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
+
+    // B-spline warps: this workgroup's row of control-grid gradients, zeroed here
+    const bool want_ctrl = DISP == kDispSpline && ctrl_part != nullptr;
+    const int32_t nctrl = 3 * J.bs.gx * J.bs.gy * J.bs.gz;
+    double *ctrl_row = want_ctrl ? ctrl_part + (int64_t)blockIdx.x * nctrl : nullptr;
+    if (want_ctrl) {
+        for (int e = threadIdx.x; e < nctrl; e += kThreads)
+            ctrl_row[e] = 0.0;
+        __syncthreads();
+    }
 
     __shared__ int s_red[kThreads / 64][6];
 
@@ -112,6 +254,10 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         // coordinates, guard and upstream gradient of the run's voxels
         float qv[4][3], gpk[4];
         bool gd[4];
+        float u[3][4];
+        if (DISP == kDispSpline)
+            spline_tile_u<kThreads, false>(J.ctrl, J.bs, TL.lx, TL.ly, x0, y0, z0, x1, y1, z1,
+                                    threadIdx.x >> 2, x, y, z, nvalid, run_ok, s_cells, u);
         {
             float rb[3];
             row_base(J.M, (float)x, (float)y, rb);
@@ -126,10 +272,14 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 const float zf = (float)(z + k);
                 float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
                       qz = coord(J.M, 2, rb, zf);
-                if (DISP) {
+                if (DISP == kDispField) {
                     qx = qx + disp[v];
                     qy = qy + disp[nvox + v];
                     qz = qz + disp[2 * nvox + v];
+                } else if (DISP == kDispSpline) {
+                    qx = qx + u[0][k];
+                    qy = qy + u[1][k];
+                    qz = qz + u[2][k];
                 }
                 qv[k][0] = qx;
                 qv[k][1] = qy;
@@ -139,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
             }
         }
         TileGeom G;
-        if (DISP) {
+        if (DISP != kDispNone) {
             // no a-priori bound with a displacement field: the footprint is the
             // range of floor(q) over the tile's guarded samples (block reduction)
             int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -168,6 +318,10 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         float tw[4][3], gk[4];
         bool live[4] = {false, false, false, false};
         float S[3] = {0.0f, 0.0f, 0.0f}, Sz[3] = {0.0f, 0.0f, 0.0f};
+        float gu[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            gu[k][0] = gu[k][1] = gu[k][2] = 0.0f;
         if (run_ok) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -234,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                         }
                     }
                 }
-                if (DISP && g_disp) {
+                if (DISP != kDispNone && g_disp) {
                     g_disp[v] = gp * dV[0];
                     g_disp[nvox + v] = gp * dV[1];
                     g_disp[2 * nvox + v] = gp * dV[2];
@@ -242,6 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const float c = gp * dV[i];
+                    gu[k][i] = c;
                     S[i] += c;
                     Sz[i] = __builtin_fmaf(c, zf, Sz[i]);
                 }
@@ -254,50 +409,53 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 acc[4 * i + 3] += (double)S[i];
             }
         }
-        if (!lds)
-            continue;                      // uniform: no barrier is skipped by part of the group
-        __syncthreads();                   // every corner read of the staged image is done
-        if (g_img) {
-            // the footprint cells become FP32 accumulators of w_c * g
-            const int cells = G.e[0] * sxy;
-            for (int c = 4 * threadIdx.x; c < cells; c += 4 * kThreads)
-                *reinterpret_cast<f32x4 *>(s_cells + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            __syncthreads();
+        if (lds) {                         // uniform: no barrier is skipped by part of the group
+            __syncthreads();               // every corner read of the staged image is done
+            if (g_img) {
+                // the footprint cells become FP32 accumulators of w_c * g
+                const int cells = G.e[0] * sxy;
+                for (int c = 4 * threadIdx.x; c < cells; c += 4 * kThreads)
+                    *reinterpret_cast<f32x4 *>(s_cells + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                __syncthreads();
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!live[k])
-                    continue;
-                const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
-                const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
-                const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
+                for (int k = 0; k < 4; ++k) {
+                    if (!live[k])
+                        continue;
+                    const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
+                    const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
+                    const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                    for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int bb = 0; bb < 2; ++bb) {
-                        const float wxy = wx[a] * wy[bb];
-                        float *row = s_cells + base[k] + a * sxy + bb * pitch;
-                        atomicAdd(row, wxy * gz0);
-                        atomicAdd(row + 1, wxy * gz1);
-                    }
+                        for (int bb = 0; bb < 2; ++bb) {
+                            const float wxy = wx[a] * wy[bb];
+                            float *row = s_cells + base[k] + a * sxy + bb * pitch;
+                            atomicAdd(row, wxy * gz0);
+                            atomicAdd(row + 1, wxy * gz1);
+                        }
+                }
+                __syncthreads();
+                // flush: one global atomic per touched in-volume footprint cell
+                const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
+                for (int c = threadIdx.x; c < cells; c += kThreads) {
+                    const float v = s_cells[c];
+                    if (v == 0.0f)
+                        continue;
+                    const int row = div_small(c, pitch, rcp_pitch);
+                    const int cz = c - row * pitch;
+                    const int cx = div_small(row, ey, rcp_ey);
+                    const int cy = row - cx * ey;
+                    const int gx = G.lo[0] + cx, gy = G.lo[1] + cy, gz = G.lo[2] + cz;
+                    if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
+                        (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
+                        unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz, v);
+                }
+                __syncthreads();           // LDS is reused next
             }
-            __syncthreads();
-            // flush: one global atomic per touched in-volume footprint cell
-            const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
-            for (int c = threadIdx.x; c < cells; c += kThreads) {
-                const float v = s_cells[c];
-                if (v == 0.0f)
-                    continue;
-                const int row = div_small(c, pitch, rcp_pitch);
-                const int cz = c - row * pitch;
-                const int cx = div_small(row, ey, rcp_ey);
-                const int cy = row - cx * ey;
-                const int gx = G.lo[0] + cx, gy = G.lo[1] + cy, gz = G.lo[2] + cz;
-                if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
-                    (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
-                    unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz, v);
-            }
-            __syncthreads();               // LDS is restaged by the next tile
         }
+        if (want_ctrl)
+            ctrl_adjoint_tile(J.bs, x0, y0, z0, x1, y1, z1, threadIdx.x >> 2, zr, gu, s_cells,
+                              ctrl_row);
     }
 
     if (!partials)
@@ -327,6 +485,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce12(const double *__restrict_
 #pragma unroll
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
+
     for (int r = threadIdx.x; r < n; r += kThreads)
 #pragma unroll
         for (int i = 0; i < 12; ++i)
@@ -348,15 +507,83 @@ __global__ __launch_bounds__(kThreads) void k_reduce12(const double *__restrict_
     }
 }
 
+// Sum the per-workgroup rows of control-grid gradients in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_reduce_ctrl(const double *__restrict__ part,
+                                                          int32_t rows, int32_t n,
+                                                          float *__restrict__ out)
+{
+    const int32_t e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n)
+        return;
+    double s = 0.0;
+    for (int32_t r = 0; r < rows; ++r)
+        s += part[(int64_t)r * n + e];
+    out[e] = (float)s;
+}
+
+// Host replica of bs_index (the same single FP32 multiply and floor).
+static int32_t host_bs_index(int64_t p, float inv_h, int32_t G)
+{
+    const float s = (float)p * inv_h;
+    return (int32_t)std::fmin(std::floor(s), (float)(G - 4));
+}
+
+// Largest number of controls any tile of extent 2^l touches along one axis.
+static int32_t max_window(int64_t n, int l, float inv_h, int32_t G)
+{
+    int32_t w = 0;
+    for (int64_t p0 = 0; p0 < n; p0 += (int64_t)1 << l) {
+        const int64_t p1 = std::min(p0 + ((int64_t)1 << l), n) - 1;
+        w = std::max(w, host_bs_index(p1, inv_h, G) - host_bs_index(p0, inv_h, G) + 4);
+    }
+    return w;
+}
+
+bool bwd_spline_eval_ok(const BsplineGeom &B)
+{
+    return max_window(B.oz, kBwdTiling.lz, B.inv_hz, B.gz) <= kSplineWindow;
+}
+
+bool bwd_ctrl_fused(const BsplineGeom &B)
+{
+    if (3 * (int64_t)B.gx * B.gy * B.gz > kCtrlMaxEntries)
+        return false;
+    return bwd_spline_eval_ok(B) &&
+           max_window(B.ox, kBwdTiling.lx, B.inv_hx, B.gx) <= kSplineWindow &&
+           max_window(B.oy, kBwdTiling.ly, B.inv_hy, B.gy) <= kSplineWindow;
+}
+
+template <int DISP>
+static void launch_bwd_t(const FwdJob &J, int grid, size_t lds, hipStream_t s, const float *g,
+                         float *g_img, float *g_disp, double *part, double *ctrl_part, int nt,
+                         int32_t cells)
+{
+    if (J.dtype == kI16)
+        hipLaunchKernelGGL((k_warp_bwd<int16_t, DISP>), dim3(grid), dim3(kThreads), lds, s, J, g,
+                           g_img, g_disp, part, ctrl_part, nt, cells);
+    else
+        hipLaunchKernelGGL((k_warp_bwd<float, DISP>), dim3(grid), dim3(kThreads), lds, s, J, g,
+                           g_img, g_disp, part, ctrl_part, nt, cells);
+}
+
 hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float *g_disp,
-                           double *g_M, double *partials, hipStream_t s)
+                           double *g_M, double *partials, double *ctrl_part, float *g_ctrl,
+                           hipStream_t s)
 {
     FwdJob J = J0;
     J.tiles_x = (J.ox + 7) >> 3;
     J.tiles_y = (J.oy + 7) >> 3;
     J.tiles_z = (J.oz + 15) >> 4;
     const int64_t ntiles = (int64_t)J.tiles_x * J.tiles_y * J.tiles_z;
+    const int32_t nctrl = 3 * J.bs.gx * J.bs.gy * J.bs.gz;
     if (ntiles == 0) {
+        if (g_ctrl && nctrl > 0) {     // no tiles: the rows are not read
+            hipLaunchKernelGGL(k_reduce_ctrl, dim3((nctrl + kThreads - 1) / kThreads),
+                               dim3(kThreads), 0, s, ctrl_part, 0, nctrl, g_ctrl);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
         if (g_M) {
             hipLaunchKernelGGL(k_reduce12, dim3(1), dim3(kThreads), 0, s, partials, 0, g_M);
             return hipGetLastError();
@@ -364,32 +591,33 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
         return hipSuccess;
     }
     const int grid = (int)bwd_grid(ntiles);
-    // LDS cells sized for the largest footprint of any tile (a displacement field
-    // has no a-priori bound: the full reservation, used when a tile fits it)
+    // LDS cells sized for the largest footprint of any tile (a displacement has
+    // no a-priori bound: the full reservation, used when a tile fits it)
+    const bool displaced = J.disp || J.ctrl;
     const int32_t cells =
-        J.disp ? kBwdLdsCells : std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells);
+        displaced ? kBwdLdsCells : std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells);
     const size_t lds = (size_t)cells * sizeof(float);
     double *part = g_M ? partials : nullptr;
-    const bool disp = J.disp != nullptr;
+    double *cpart = g_ctrl ? ctrl_part : nullptr;
     const int nt = (int)ntiles;
-    if (J.dtype == kI16) {
-        if (disp)
-            hipLaunchKernelGGL((k_warp_bwd<int16_t, true>), dim3(grid), dim3(kThreads), lds, s, J,
-                               g, g_img, g_disp, part, nt, cells);
-        else
-            hipLaunchKernelGGL((k_warp_bwd<int16_t, false>), dim3(grid), dim3(kThreads), lds, s,
-                               J, g, g_img, g_disp, part, nt, cells);
-    } else {
-        if (disp)
-            hipLaunchKernelGGL((k_warp_bwd<float, true>), dim3(grid), dim3(kThreads), lds, s, J,
-                               g, g_img, g_disp, part, nt, cells);
-        else
-            hipLaunchKernelGGL((k_warp_bwd<float, false>), dim3(grid), dim3(kThreads), lds, s, J,
-                               g, g_img, g_disp, part, nt, cells);
-    }
+    if (J.ctrl)
+        launch_bwd_t<kDispSpline>(J, grid, lds, s, g, g_img, g_disp, part, cpart, nt, cells);
+    else if (J.disp)
+        launch_bwd_t<kDispField>(J, grid, lds, s, g, g_img, g_disp, part, nullptr, nt, cells);
+    else
+        launch_bwd_t<kDispNone>(J, grid, lds, s, g, g_img, nullptr, part, nullptr, nt, cells);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !g_M)
+    if (e != hipSuccess)
         return e;
+    if (cpart) {
+        hipLaunchKernelGGL(k_reduce_ctrl, dim3((nctrl + kThreads - 1) / kThreads), dim3(kThreads),
+                           0, s, cpart, grid, nctrl, g_ctrl);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (!g_M)
+        return hipSuccess;
     hipLaunchKernelGGL(k_reduce12, dim3(1), dim3(kThreads), 0, s, partials, grid, g_M);
     return hipGetLastError();
 }

@@ -210,72 +210,6 @@ __device__ __forceinline__ void fwd_box(const FwdJob &J, const TileGeom &G, cons
         fwd_box_l<T, LT, ALIGNED, false, DISP>(J, G, SL, s_lds, lds_cells, Q);
 }
 
-// Displacement of the runs of a displacement tile evaluated from the control
-// grid.  The row profiles of the tile's rows over its z-control window go to
-// LDS (free until the footprint is staged); each thread then contracts z for
-// its own voxels.  The operations and their order are those of the upsampling
-// kernel, so u equals the dense field bit for bit.  A window of more than
-// kProfCtrl controls (controls closer than about 4 voxels along z) evaluates
-// the profiles per voxel instead.
-constexpr int kProfCtrl = 8;
-
-__device__ __forceinline__ void spline_u(const FwdJob &J, const Tiling &TL, int x0, int y0, int z0,
-                                         int x1, int y1, int z1, int rr, int x, int y, int z,
-                                         int nvalid, bool mine, float *s_prof, float (&u)[3][4])
-{
-    const BsplineGeom &B = J.bs;
-    const int izl = bs_index(z0, B.inv_hz, B.gz);
-    const int ncz = bs_index(z1, B.inv_hz, B.gz) - izl + 4;
-    if (ncz <= kProfCtrl) {
-        const int per_row = 3 * ncz;
-        const int nent = per_row << (TL.lx + TL.ly);
-        for (int e = threadIdx.x; e < nent; e += kThreads) {
-            const int row = e / per_row;
-            const int rem = e - row * per_row;
-            const int comp = rem / ncz, c = rem - comp * ncz;
-            const int px = min(x0 + (row >> TL.ly), x1);
-            const int py = min(y0 + (row & ((1 << TL.ly) - 1)), y1);
-            s_prof[e] = bs_profile(J.ctrl, B, comp, px, py, izl + c);
-        }
-        __syncthreads();
-        if (!mine)
-            return;
-        const float *P = s_prof + rr * per_row - izl;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k >= nvalid)
-                break;
-            int32_t iz;
-            float tz, Bz[4];
-            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
-            bs_basis(tz, Bz);
-#pragma unroll
-            for (int comp = 0; comp < 3; ++comp) {
-                float s = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    s = __builtin_fmaf(Bz[c], P[comp * ncz + iz + c], s);
-                u[comp][k] = s;
-            }
-        }
-    } else if (mine) {
-        for (int k = 0; k < nvalid; ++k) {
-            int32_t iz;
-            float tz, Bz[4];
-            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
-            bs_basis(tz, Bz);
-#pragma unroll
-            for (int comp = 0; comp < 3; ++comp) {
-                float s = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    s = __builtin_fmaf(Bz[c], bs_profile(J.ctrl, B, comp, x, y, iz + c), s);
-                u[comp][k] = s;
-            }
-        }
-    }
-}
-
 // One output tile, processed as sub-tiles of the job's sub-tile shape (the
 // whole tile unless its input footprint would not fit the LDS reservation).
 // ALIGNED: the output z extent is a multiple of 4, so every run is one noise
@@ -308,8 +242,8 @@ __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling
         const int nvalid = min(4, J.oz - z);
         float u[3][4];
         if (DISP == kDispSpline)
-            spline_u(J, TL, x0, y0, z0, x1, y1, z1, rr, x, y, z, nvalid, mine,
-                     reinterpret_cast<float *>(s_lds), u);
+            spline_tile_u<kThreads>(J.ctrl, J.bs, TL.lx, TL.ly, x0, y0, z0, x1, y1, z1, rr, x, y,
+                                    z, nvalid, mine, reinterpret_cast<float *>(s_lds), u);
         RunQ Q;
         int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
         if (mine) {
@@ -515,7 +449,7 @@ static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32
 constexpr Tiling kDispTiling = {3, 3, 4};
 constexpr int32_t kDispLdsCells = 10224;
 static_assert(1 << (3 + 3 + 4 - 2) == kThreads, "one run of a displacement tile per thread");
-static_assert(3 * kDispLdsCells >= 64 * 3 * kProfCtrl * (int32_t)sizeof(float),
+static_assert(3 * kDispLdsCells >= 64 * 3 * kSplineWindow * (int32_t)sizeof(float),
               "the B-spline row profiles of a tile fit its smallest footprint reservation");
 
 hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s)

@@ -228,6 +228,34 @@ def warp_displacement_backward(img, M, disp, grad_out, fill=-1000.0, want_img=Tr
     return _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp)
 
 
+def warp_bspline_backward(img, M, ctrl, grad_out, fill=-1000.0, want_img=True, want_M=True,
+                          want_ctrl=True):
+    """Adjoint of warp_bspline: (grad_img, grad_M float64[12], grad_ctrl
+    [3][Gx][Gy][Gz]), each None when not wanted."""
+    _require(img, "img", (torch.float32, torch.int16))
+    _require(grad_out, "grad_out", (torch.float32,))
+    _require(ctrl, "ctrl", (torch.float32,), ndim=4)
+    if ctrl.shape[0] != 3:
+        raise ValueError(f"ctrl: expected [3][Gx][Gy][Gz], got {tuple(ctrl.shape)}")
+    dev = img.device
+    G = (ctypes.c_int64 * 3)(*ctrl.shape[1:])
+    od = (ctypes.c_int64 * 3)(*grad_out.shape)
+    L = _lib.load()
+    g_img = torch.zeros(tuple(img.shape), dtype=torch.float32, device=dev) if want_img else None
+    g_M = torch.empty(12, dtype=torch.float64, device=dev) if want_M else None
+    g_ctrl = torch.empty_like(ctrl) if want_ctrl else None
+    ws_bytes = int(L.ctaug_warp_bspline_backward_workspace(od, G))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    vi, vg = vol(img), vol(grad_out)
+    vgi = vol(g_img) if want_img else None
+    p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
+    st = L.ctaug_warp_bspline_backward(ctypes.byref(vi), _M32(M), p(ctrl), G, float(fill),
+                                       ctypes.byref(vg), _ref(vgi), p(g_M), p(g_ctrl), p(ws),
+                                       ws_bytes, _stream())
+    _lib.check(st, "ctaug_warp_bspline_backward")
+    return g_img, g_M, g_ctrl
+
+
 def bspline_upsample(ctrl, out_dim, out=None):
     """Dense displacement [3][Xo][Yo][Zo] from a control grid [3][Gx][Gy][Gz]."""
     _require(ctrl, "ctrl", (torch.float32,), ndim=4)

@@ -286,6 +286,39 @@ def test_fused_bspline_warp_validation(L):
     assert call(None, g, out_vol=vol((0, 32, 32), data=None)) == OK
 
 
+def test_fused_bspline_backward_workspace_and_validation(L):
+    r = ctypes.byref
+    od = (ctypes.c_int64 * 3)(64, 64, 64)
+    g8 = (ctypes.c_int64 * 3)(8, 8, 8)
+    rows = L.ctaug_warp_backward_workspace(od) // 96
+    m = -(-rows * 96 // 256) * 256
+    # 8^3 grid over 64^3: the fused route, one row of control gradients per workgroup
+    assert L.ctaug_warp_bspline_backward_workspace(od, g8) == m + rows * 3 * 512 * 8
+    # controls closer than 2 voxels along z: the dense route (field, its gradient,
+    # the B-spline adjoint's workspace)
+    gz = (ctypes.c_int64 * 3)(8, 8, 60)
+    dense = L.ctaug_warp_bspline_backward_workspace(od, gz)
+    field = -(-3 * 64 ** 3 * 4 // 256) * 256
+    assert dense == m + 2 * field + L.ctaug_bspline_adjoint_workspace(od, gz)
+    assert L.ctaug_warp_bspline_backward_workspace(od, (ctypes.c_int64 * 3)(3, 8, 8)) == 0
+    assert L.ctaug_warp_bspline_backward_workspace(None, g8) == 0
+    img, g = vol((8, 8, 8)), vol((64, 64, 64))
+    need = L.ctaug_warp_bspline_backward_workspace(od, g8)
+
+    def call(ctrl=FAKE, G=g8, gimg=None, gM=FAKE, gc=FAKE, ws=FAKE, nbytes=need, gout=g):
+        return L.ctaug_warp_bspline_backward(r(img), mat(), ctrl, G, 0.0, r(gout),
+                                             r(gimg) if gimg is not None else None, gM, gc, ws,
+                                             nbytes, None)
+
+    assert call(ws=None) == EWORKSPACE
+    assert call(nbytes=need - 8) == EWORKSPACE
+    assert call(G=None) == EINVAL
+    assert call(G=(ctypes.c_int64 * 3)(8, 65, 8)) == ESHAPE
+    assert call(ctrl=None) == EINVAL
+    assert call(gimg=vol((8, 8, 9))) == ESHAPE
+    assert call(gout=vol((64, 64, 64), I16)) == EDTYPE
+
+
 # -- batch plan ---------------------------------------------------------------
 
 def _job(in_dims=(8, 8, 8), out_dims=(4, 4, 4), dtype=I16):

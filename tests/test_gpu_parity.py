@@ -5,6 +5,8 @@ Bars: labels and Philox words bit-exact; Box-Muller Gaussians within
 windowed [0,1] output and R = 1000 HU for HU output; gradients within 1e-4
 normwise per tensor (and elementwise 1e-4 * max(|ref|, 1e-2 ||ref||_inf)).
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -352,11 +354,14 @@ def test_displacement_warp_parity_given_field(amp, out_dim, dtype):
 @pytest.mark.parametrize("out_dim,grid", [((64, 48, 40), (8, 8, 8)), ((33, 17, 9), (6, 5, 7)),
                                           ((1, 12, 16), (4, 4, 4))])
 def test_bspline_upsample_parity(out_dim, grid):
+    """Equal bit for bit to the oracle's FP32 parity-mode field, and within
+    FP32 rounding of the FP64 definition."""
     rng = np.random.default_rng(7)
     C = (4.0 * rng.standard_normal((3,) + grid)).astype(np.float32)
-    u = ctaug.bspline_upsample(_t(C), out_dim)
+    u = _np(ctaug.bspline_upsample(_t(C), out_dim))
+    assert np.array_equal(u.view(np.uint32), oracle.bspline_upsample_f32(C, out_dim).view(np.uint32))
     ref = oracle.bspline_upsample(C, out_dim)
-    err = np.abs(_np(u).astype(np.float64) - ref).max()
+    err = np.abs(u.astype(np.float64) - ref).max()
     assert err <= 1e-5 * np.abs(C).max(), err
 
 
@@ -367,45 +372,6 @@ def test_bspline_adjoint_parity(out_dim, grid):
     gc = ctaug.bspline_upsample_adjoint(_t(g), grid)
     ref = oracle.bspline_adjoint(g.astype(np.float64), grid)
     assert_grad(_np(gc), ref, "g_ctrl")
-
-
-def _smooth_volume(dims, seed):
-    """Seeded smooth HU volume (sums of low-frequency sinusoids, |grad| below
-    about 400 HU per voxel)."""
-    rng = np.random.default_rng(seed)
-    x, y, z = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in dims], indexing="ij")
-    ph = rng.uniform(0, 2 * np.pi, 3)
-    v = (300.0 * np.sin(2 * np.pi * x / 23 + ph[0]) * np.cos(2 * np.pi * y / 19 + ph[1])
-         + 250.0 * np.sin(2 * np.pi * z / 17 + ph[2]) - 200.0)
-    return v.astype(np.float32)
-
-
-def _assert_labels_up_to_ties(got, ref, lbl, M, u64, label_fill=0, eps=1e-3):
-    """Nearest-neighbour labels of a warp whose displacement the two sides
-    round differently: equal wherever q + 0.5 is farther than eps from an
-    integer on every axis; elsewhere the label of one of the candidate voxels."""
-    od = got.shape
-    p = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in od], indexing="ij"))
-    A = np.asarray(M, np.float64).reshape(3, 4)
-    q = np.einsum("ij,jxyz->ixyz", A[:, :3], p) + A[:, 3][:, None, None, None] + u64
-    r = q + 0.5
-    tie = np.abs(r - np.round(r)) < eps
-    amb = tie.any(axis=0)
-    assert np.array_equal(got[~amb], ref[~amb])
-    assert amb.mean() < 0.02
-    n = lbl.shape
-    for idx in zip(*np.nonzero(amb & (got != ref))):
-        cands = []
-        for i in range(3):
-            j = int(np.floor(r[(i,) + idx]))
-            cands.append({j, j - 1, j + 1} if tie[(i,) + idx] else {j})
-        ok = set()
-        for jx in cands[0]:
-            for jy in cands[1]:
-                for jz in cands[2]:
-                    inside = 0 <= jx < n[0] and 0 <= jy < n[1] and 0 <= jz < n[2]
-                    ok.add(int(lbl[jx, jy, jz]) if inside else label_fill)
-        assert int(got[idx]) in ok, (idx, got[idx], ok)
 
 
 @pytest.mark.parametrize("in_dim,out_dim,grid,dtype,amp", [
@@ -432,27 +398,94 @@ def test_warp_bspline_equals_upsample_then_warp(in_dim, out_dim, grid, dtype, am
     assert np.array_equal(_np(lout), _np(lout2))
 
 
-@pytest.mark.parametrize("out_dim,grid,windowed", [((44, 40, 36), (8, 8, 8), True),
-                                                   ((37, 29, 23), (6, 7, 5), False)])
-def test_warp_bspline_parity_with_oracle_chain(out_dim, grid, windowed):
-    """Fused nonrigid warp against the oracle's own chain (FP64 B-spline field
-    rounded to FP32, then the warp).  The two fields differ by FP32 rounding of
-    the spline sum, so intensities are compared on a smooth volume (the error
-    |grad I| |du| stays far below the bar) and labels up to rounding ties."""
+@pytest.mark.parametrize("out_dim,grid,windowed,dtype", [
+    ((44, 40, 36), (8, 8, 8), True, np.int16),
+    ((37, 29, 23), (6, 7, 5), False, np.float32),
+    ((20, 18, 52), (5, 6, 40), True, np.float32),     # per-voxel profiles
+])
+def test_warp_bspline_parity_with_oracle(out_dim, grid, windowed, dtype):
+    """Fused nonrigid warp against the oracle warp with the oracle's FP32
+    parity-mode field: labels bit-exact, intensities within 1e-5."""
     in_dim = (48, 44, 40)
     rng = np.random.default_rng(61 + grid[0])
-    img = _smooth_volume(in_dim, seed=3)
-    _, lbl = phantom_pair(in_dim, seed=8)
+    img, lbl = phantom_pair(in_dim, seed=8)
     prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
     _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
     C = (4.0 * rng.standard_normal((3,) + grid)).astype(np.float32)
-    rg = AugmentRanges(window=windowed)
-    ph = draw_photo(rng, rg, seed=17, volume_id=4)
-    out, lout = ctaug.warp_bspline(_t(img), M, _t(C), lbl=_t(lbl), photo=ph, out_dim=out_dim)
-    u64 = oracle.bspline_upsample(C, out_dim)
-    ref, lref = oracle.warp(img, M, out_dim, lbl=lbl, disp=u64.astype(np.float32), photo=ph)
+    ph = draw_photo(rng, AugmentRanges(window=windowed), seed=17, volume_id=4)
+    out, lout = ctaug.warp_bspline(_t(img.astype(dtype)), M, _t(C), lbl=_t(lbl), photo=ph,
+                                   out_dim=out_dim)
+    u = oracle.bspline_upsample_f32(C, out_dim)
+    ref, lref = oracle.warp(img, M, out_dim, lbl=lbl, disp=u, photo=ph)
+    assert np.array_equal(_np(lout), lref)
     assert_intensity(_np(out), ref, windowed=windowed, what="fused B-spline warp")
-    _assert_labels_up_to_ties(_np(lout), lref, lbl, M, u64)
+
+
+@pytest.mark.parametrize("in_dim,out_dim,grid,dtype,fused", [
+    ((40, 36, 30), (44, 40, 36), (8, 8, 8), np.float32, True),
+    ((40, 36, 30), (37, 29, 23), (6, 7, 5), np.int16, True),      # ragged tiles
+    ((24, 20, 60), (20, 18, 52), (5, 6, 40), np.float32, False),  # z controls < 2 voxels apart
+    ((40, 36, 30), (48, 40, 44), (10, 10, 10), np.float32, False),  # 3000 control entries
+])
+def test_warp_bspline_backward_parity(in_dim, out_dim, grid, dtype, fused):
+    """Adjoint of the fused nonrigid warp (image, M and control grid) against
+    the oracle's warp adjoint, on its FP32 parity-mode field, followed by its
+    B-spline adjoint; both the fused control-grid reduction and the dense
+    route (grids it does not take) are covered."""
+    rng = np.random.default_rng(71 + grid[2])
+    img, _ = phantom_pair(in_dim, seed=12)
+    img = img.astype(dtype)
+    prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    C = (3.0 * rng.standard_normal((3,) + grid)).astype(np.float32)
+    u = oracle.bspline_upsample_f32(C, out_dim)
+    g = rng.standard_normal(out_dim).astype(np.float32)
+    od = (ctypes.c_int64 * 3)(*out_dim)
+    G = (ctypes.c_int64 * 3)(*grid)
+    L = ctaug._lib.load()
+    m_bytes = ctaug.ops.warp_backward_workspace(out_dim)     # rows x 12 doubles
+    ws_fused = -(-m_bytes // 256) * 256 + (m_bytes // 96) * 3 * int(np.prod(grid)) * 8
+    assert (int(L.ctaug_warp_bspline_backward_workspace(od, G)) == ws_fused) == fused
+    g_img, g_M, g_c = ctaug.warp_bspline_backward(_t(img), M, _t(C), _t(g))
+    r_img, r_M, r_u = oracle.warp_backward(img, M, g, disp=u, want_u=True)
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
+    assert_grad(_np(g_c), oracle.bspline_adjoint(r_u, grid), "g_ctrl")
+    # deterministic: a second run gives the same bits for M and the control grid
+    _, g_M2, g_c2 = ctaug.warp_bspline_backward(_t(img), M, _t(C), _t(g), want_img=False)
+    assert np.array_equal(_np(g_M).view(np.uint64), _np(g_M2).view(np.uint64))
+    assert np.array_equal(_np(g_c).view(np.uint32), _np(g_c2).view(np.uint32))
+
+
+def test_warp_bspline_backward_empty_output_zeroes_gradients():
+    img = _t(np.zeros((8, 8, 8), np.float32))
+    C = _t(np.ones((3, 5, 5, 5), np.float32))
+    g = torch.empty((0, 8, 8), dtype=torch.float32, device=DEV)
+    _, g_M, g_c = ctaug.warp_bspline_backward(img, np.eye(3, 4).ravel(), C, g, want_img=False)
+    assert not _np(g_M).any() and not _np(g_c).any()
+
+
+def test_autograd_fused_bspline_warp():
+    """torch.autograd through the fused nonrigid warp against the oracle."""
+    from paper_1811_11226_amd import autograd as ag
+    rng = np.random.default_rng(44)
+    dims = (26, 22, 30)
+    img_np, _ = phantom_pair(dims, seed=14)
+    img_np = img_np.astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M32 = ctaug.affine_matrix(prm, dims, dims)
+    ctrl = rng.normal(0.0, 2.0, (3, 7, 6, 8)).astype(np.float32)
+    u = oracle.bspline_upsample_f32(ctrl, dims)
+    g = rng.standard_normal(dims).astype(np.float32)
+    img = _t(img_np).requires_grad_(True)
+    M = torch.tensor(M32.astype(np.float64), requires_grad=True)
+    c = _t(ctrl).requires_grad_(True)
+    out = ag.warp_bspline(img, M, c)
+    (out * _t(g)).sum().backward()
+    r_img, r_M, r_u = oracle.warp_backward(img_np, M32, g, disp=u, want_u=True)
+    assert_grad(_np(img.grad), r_img, "autograd g_img")
+    assert_grad(M.grad.numpy(), r_M, "autograd g_M")
+    assert_grad(_np(c.grad), oracle.bspline_adjoint(r_u, (7, 6, 8)), "autograd g_ctrl")
 
 
 # ---------------------------------------------------------------------------
@@ -575,20 +608,13 @@ def test_autograd_affine_and_nonrigid_chain():
     assert_grad(M.grad.numpy(), r_M, "autograd g_M")
 
     ctrl = rng.normal(0.0, 2.0, (3, 6, 6, 6)).astype(np.float32)
-    # the oracle's own field; the upstream gradient is zeroed where a sample
-    # lies within 1e-3 of a cell boundary, where dV/dq jumps and the two FP32
-    # roundings of u could select different cells
-    u64 = oracle.bspline_upsample(ctrl, dims)
-    p = np.stack(np.meshgrid(*[np.arange(n, dtype=np.float64) for n in dims], indexing="ij"))
-    A = M32.astype(np.float64).reshape(3, 4)
-    q = np.einsum("ij,jxyz->ixyz", A[:, :3], p) + A[:, 3][:, None, None, None] + u64
-    g2 = np.where((np.abs(q - np.round(q)) < 1e-3).any(axis=0), 0.0, g).astype(np.float32)
+    u_ref = oracle.bspline_upsample_f32(ctrl, dims)        # the oracle's parity-mode field
     c = _t(ctrl).requires_grad_(True)
     u = ag.bspline_upsample(c, dims)
     out2 = ag.warp_displacement(_t(img_np), torch.tensor(M32.astype(np.float64)), u)
-    (out2 * _t(g2)).sum().backward()
-    _, _, r_u = oracle.warp_backward(img_np, M32, g2, disp=u64.astype(np.float32), want_img=False,
-                                     want_M=False, want_u=True)
+    (out2 * _t(g)).sum().backward()
+    _, _, r_u = oracle.warp_backward(img_np, M32, g, disp=u_ref, want_img=False, want_M=False,
+                                     want_u=True)
     assert_grad(_np(c.grad), oracle.bspline_adjoint(r_u, (6, 6, 6)), "autograd g_ctrl")
 
 

@@ -486,6 +486,23 @@ def test_bspline_partition_of_unity_and_linear_precision():
         np.testing.assert_allclose(u[comp], ref, rtol=0, atol=1e-11)
 
 
+@pytest.mark.parametrize("G,out_dim", [((8, 7, 9), (17, 13, 10)), ((4, 4, 4), (1, 9, 30)),
+                                       ((6, 5, 40), (20, 18, 52)), ((8, 8, 8), (64, 48, 40))])
+def test_bspline_f32_parity_mode_within_rounding_of_definition(G, out_dim):
+    """The FP32 parity-mode field differs from the FP64 definition only by
+    rounding (u = 2^-24): each of the 64 terms carries at most about 20u
+    relative error from the basis and the fmaf chains, and the weights sum to
+    1, so 20u max|C|; the cell coordinate s = p * inv_h is off by at most 2u s
+    <= 2u (G - 3) per axis, and |du/ds| <= 2 max|C| per axis."""
+    rng = np.random.default_rng(sum(G) + sum(out_dim))
+    C = (5.0 * rng.standard_normal((3,) + G)).astype(np.float32)
+    u32 = oracle.bspline_upsample_f32(C, out_dim)
+    u64 = oracle.bspline_upsample(C.astype(np.float64), out_dim)
+    assert u32.dtype == np.float32 and u32.shape == u64.shape
+    bound = 2.0 ** -24 * (20 + 12 * (max(G) - 3)) * np.abs(C).max()
+    assert np.abs(u32 - u64).max() <= bound
+
+
 def test_bspline_adjoint_identity():
     rng = np.random.default_rng(19)
     G = (8, 8, 8)
