@@ -510,7 +510,7 @@ extern "C" size_t ctaug_warp_bspline_backward_workspace(const int64_t out_dim[3]
     const size_t m = align256((size_t)rows * 12 * sizeof(double));
     const BsplineGeom B = bspline_geom(G, out_dim);
     if (bwd_ctrl_fused(B))
-        return m + (size_t)rows * 3 * G[0] * G[1] * G[2] * sizeof(double);
+        return m + (size_t)ctrl_reduce_doubles(rows, 3 * G[0] * G[1] * G[2]) * sizeof(double);
     const size_t field = align256((size_t)(3 * nelem(out_dim)) * sizeof(float));
     return m + 2 * field + (size_t)bspline_adj_ws_bytes(out_dim, G);
 }

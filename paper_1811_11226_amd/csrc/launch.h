@@ -36,11 +36,13 @@ int64_t bwd_partial_rows(int64_t ox, int64_t oy, int64_t oz);
 // Adjoint of a warp.  A control grid (J.ctrl) requires bwd_spline_eval_ok(J.bs)
 // (every tile's z window of controls fits the kernel's row profiles); its
 // gradient g_ctrl is fused into the adjoint when bwd_ctrl_fused(J.bs) holds,
-// with ctrl_part holding bwd_partial_rows() rows of 3 Gx Gy Gz doubles.
+// with ctrl_part holding ctrl_reduce_doubles(bwd_partial_rows(), 3 Gx Gy Gz)
+// doubles (the per-workgroup rows, then the row-group sums).
 // Otherwise the caller materialises the field and uses the dense path.
 hipError_t launch_warp_bwd(const FwdJob &J, const float *g, float *g_img, float *g_disp,
                            double *g_M, double *partials, double *ctrl_part, float *g_ctrl,
                            hipStream_t s);
+int64_t ctrl_reduce_doubles(int64_t rows, int64_t nctrl);
 bool bwd_spline_eval_ok(const BsplineGeom &B);
 bool bwd_ctrl_fused(const BsplineGeom &B);
 

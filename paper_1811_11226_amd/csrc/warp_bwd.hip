@@ -78,8 +78,22 @@ __device__ __forceinline__ void cell_gradient(const float K[8], const float tt[3
 }
 
 // Largest control grid (3 Gx Gy Gz entries) whose gradient is fused into the
-// adjoint kernel: one FP64 row per workgroup in the workspace.
+// adjoint kernel: FP32 accumulators in LDS beside a footprint reservation
+// shrunk by as much, so that the workgroup's LDS stays at 48 KB; one FP64 row
+// per workgroup in the workspace; rows summed in kCtrlRowGroups groups, then
+// the groups (both in a fixed order).
 constexpr int32_t kCtrlMaxEntries = 2048;
+constexpr int32_t kSplineBwdCells = kBwdLdsCells - kCtrlMaxEntries;
+constexpr int32_t kCtrlRowGroups = 64;
+
+// v + (v of the lane at quad position q ^ 1), then ^ 2: sum over the 4 lanes
+// of a quad, in the same order on every lane (DPP quad permutes, no LDS).
+__device__ __forceinline__ float quad_sum(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+    return v;
+}
 
 // Spline weight matrix of one tile axis: Wt[p][c] = B_{c - (i(p) - i(p0))}(t(p))
 // for the 2^lp voxels p0 + p <= p1 of the axis and the window of kSplineWindow
@@ -109,16 +123,15 @@ __device__ __forceinline__ void spline_weight_entry(int e, int p0, int p1, float
 //   W[row][i][c]   = sum_z  Zw[z][c] gu_i(row, z)        (4 lanes of a row, butterfly)
 //   H[x][i][b][c]  = sum_y  Yw[y][b] W[(x, y)][i][c]
 //   R[i][a][b][c]  = sum_x  Xw[x][a] H[x][i][b][c]
-// then R is added to the workgroup's FP64 row of the workspace (each entry of
-// the row is updated by one thread per tile, tiles in a fixed order, so the
-// row is deterministic).  Every axis window must hold at most kSplineWindow
-// controls (checked on the host).  The caller guarantees that no thread reads
-// LDS on entry; ends with a barrier, which also orders the row updates of
-// consecutive tiles.
+// then R is added to the workgroup's FP32 accumulators acc (LDS, one per
+// control entry; each entry is updated by one thread per tile and tiles come
+// in a fixed order, so the sums are deterministic).  Every axis window must
+// hold at most kSplineWindow controls (checked on the host).  The caller
+// guarantees that no thread reads the scratch LDS on entry; ends with a
+// barrier.
 __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, int y0, int z0,
                                                   int x1, int y1, int z1, int rr, int zr,
-                                                  const float (&gu)[4][3], float *lds,
-                                                  double *__restrict__ row)
+                                                  const float (&gu)[4][3], float *lds, float *acc)
 {
     constexpr int NW = kSplineWindow;
     static_assert(NW == 8, "window entries are indexed with 3-bit fields");
@@ -128,6 +141,9 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
     float *W = Xw + 8 * NW;                    // [64][3][NW]
     float *H = W + 64 * 3 * NW;                // [8][3][NW][NW]
     float *R = H + 8 * 3 * NW * NW;            // [3][NW][NW][NW]
+    static_assert(16 * NW + 16 * NW + 64 * 3 * NW + 8 * 3 * NW * NW + 3 * NW * NW * NW <=
+                      kSplineBwdCells,
+                  "the tile's contraction scratch fits the footprint reservation");
     const int t = threadIdx.x;
     if (t < 16 * NW)
         spline_weight_entry(t, z0, z1, B.inv_hz, B.gz, Zw);
@@ -147,8 +163,7 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
             v = __builtin_fmaf(w1, gu[1][i], v);
             v = __builtin_fmaf(w2, gu[2][i], v);
             v = __builtin_fmaf(w3, gu[3][i], v);
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
+            v = quad_sum(v);
             if (zr == 0)
                 W[(rr * 3 + i) * NW + c] = v;
         }
@@ -195,7 +210,7 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
     for (int e = t; e < 3 * NW * NW * NW; e += kThreads) {
         const int c = e & (NW - 1), b = (e >> 3) & (NW - 1), a = (e >> 6) & (NW - 1), i = e >> 9;
         if (a < ncx && b < ncy && c < ncz)
-            row[((i * B.gx + ixl + a) * B.gy + iyl + b) * B.gz + izl + c] += (double)R[e];
+            acc[((i * B.gx + ixl + a) * B.gy + iyl + b) * B.gz + izl + c] += R[e];
     }
     __syncthreads();
 }
@@ -224,13 +239,14 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
 
-    // B-spline warps: this workgroup's row of control-grid gradients, zeroed here
+    // B-spline warps: this workgroup's control-grid gradient accumulators, in
+    // LDS after the footprint reservation
     const bool want_ctrl = DISP == kDispSpline && ctrl_part != nullptr;
     const int32_t nctrl = 3 * J.bs.gx * J.bs.gy * J.bs.gz;
-    double *ctrl_row = want_ctrl ? ctrl_part + (int64_t)blockIdx.x * nctrl : nullptr;
+    float *s_ctrl = s_cells + lds_cells;
     if (want_ctrl) {
         for (int e = threadIdx.x; e < nctrl; e += kThreads)
-            ctrl_row[e] = 0.0;
+            s_ctrl[e] = 0.0f;
         __syncthreads();
     }
 
@@ -455,8 +471,12 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         }
         if (want_ctrl)
             ctrl_adjoint_tile(J.bs, x0, y0, z0, x1, y1, z1, threadIdx.x >> 2, zr, gu, s_cells,
-                              ctrl_row);
+                              s_ctrl);
     }
+
+    if (want_ctrl)                         // the last tile ended with a barrier
+        for (int e = threadIdx.x; e < nctrl; e += kThreads)
+            ctrl_part[(int64_t)blockIdx.x * nctrl + e] = (double)s_ctrl[e];
 
     if (!partials)
         return;
@@ -507,18 +527,57 @@ __global__ __launch_bounds__(kThreads) void k_reduce12(const double *__restrict_
     }
 }
 
-// Sum the per-workgroup rows of control-grid gradients in a fixed order.
-__global__ __launch_bounds__(kThreads) void k_reduce_ctrl(const double *__restrict__ part,
-                                                          int32_t rows, int32_t n,
-                                                          float *__restrict__ out)
+// Control-grid rows, stage 1: group g (blockIdx.y) sums rows g*chunk ..
+// (g+1)*chunk - 1 in order for 64 consecutive entries (one wave, coalesced).
+__global__ __launch_bounds__(64) void k_reduce_ctrl_rows(const double *__restrict__ part,
+                                                        int32_t rows, int32_t chunk, int32_t n,
+                                                        double *__restrict__ groups)
+{
+    const int32_t e = blockIdx.x * 64 + threadIdx.x;
+    if (e >= n)
+        return;
+    const int32_t r0 = blockIdx.y * chunk, r1 = min(r0 + chunk, rows);
+    double s = 0.0;
+    for (int32_t r = r0; r < r1; ++r)
+        s += part[(int64_t)r * n + e];
+    groups[(int64_t)blockIdx.y * n + e] = s;
+}
+
+// Stage 2: out[e] = sum over the groups in order (0 when there are none).
+__global__ __launch_bounds__(kThreads) void k_reduce_ctrl_groups(const double *__restrict__ groups,
+                                                                 int32_t ngroups, int32_t n,
+                                                                 float *__restrict__ out)
 {
     const int32_t e = blockIdx.x * kThreads + threadIdx.x;
     if (e >= n)
         return;
     double s = 0.0;
-    for (int32_t r = 0; r < rows; ++r)
-        s += part[(int64_t)r * n + e];
+    for (int32_t g = 0; g < ngroups; ++g)
+        s += groups[(int64_t)g * n + e];
     out[e] = (float)s;
+}
+
+int64_t ctrl_reduce_doubles(int64_t rows, int64_t nctrl)
+{
+    return (rows + std::min<int64_t>(rows, kCtrlRowGroups)) * nctrl;
+}
+
+static hipError_t reduce_ctrl(const double *part, int32_t rows, int32_t n, float *out,
+                              hipStream_t s)
+{
+    const int32_t ngroups = std::min(rows, kCtrlRowGroups);
+    const double *groups = part + (int64_t)rows * n;
+    if (ngroups > 0) {
+        const int32_t chunk = (rows + ngroups - 1) / ngroups;
+        hipLaunchKernelGGL(k_reduce_ctrl_rows, dim3((n + 63) / 64, ngroups), dim3(64), 0, s, part,
+                           rows, chunk, n, const_cast<double *>(groups));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_reduce_ctrl_groups, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       s, groups, ngroups, n, out);
+    return hipGetLastError();
 }
 
 // Host replica of bs_index (the same single FP32 multiply and floor).
@@ -577,10 +636,8 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
     const int64_t ntiles = (int64_t)J.tiles_x * J.tiles_y * J.tiles_z;
     const int32_t nctrl = 3 * J.bs.gx * J.bs.gy * J.bs.gz;
     if (ntiles == 0) {
-        if (g_ctrl && nctrl > 0) {     // no tiles: the rows are not read
-            hipLaunchKernelGGL(k_reduce_ctrl, dim3((nctrl + kThreads - 1) / kThreads),
-                               dim3(kThreads), 0, s, ctrl_part, 0, nctrl, g_ctrl);
-            hipError_t e = hipGetLastError();
+        if (g_ctrl && nctrl > 0) {     // no tiles, no rows: zeros
+            hipError_t e = reduce_ctrl(ctrl_part, 0, nctrl, g_ctrl, s);
             if (e != hipSuccess)
                 return e;
         }
@@ -595,8 +652,10 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
     // no a-priori bound: the full reservation, used when a tile fits it)
     const bool displaced = J.disp || J.ctrl;
     const int32_t cells =
-        displaced ? kBwdLdsCells : std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells);
-    const size_t lds = (size_t)cells * sizeof(float);
+        J.ctrl ? kSplineBwdCells
+               : displaced ? kBwdLdsCells
+                           : std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells);
+    const size_t lds = (size_t)(J.ctrl ? kBwdLdsCells : cells) * sizeof(float);
     double *part = g_M ? partials : nullptr;
     double *cpart = g_ctrl ? ctrl_part : nullptr;
     const int nt = (int)ntiles;
@@ -610,9 +669,7 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
     if (e != hipSuccess)
         return e;
     if (cpart) {
-        hipLaunchKernelGGL(k_reduce_ctrl, dim3((nctrl + kThreads - 1) / kThreads), dim3(kThreads),
-                           0, s, cpart, grid, nctrl, g_ctrl);
-        e = hipGetLastError();
+        e = reduce_ctrl(cpart, grid, nctrl, g_ctrl, s);
         if (e != hipSuccess)
             return e;
     }

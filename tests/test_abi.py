@@ -293,7 +293,8 @@ def test_fused_bspline_backward_workspace_and_validation(L):
     rows = L.ctaug_warp_backward_workspace(od) // 96
     m = -(-rows * 96 // 256) * 256
     # 8^3 grid over 64^3: the fused route, one row of control gradients per workgroup
-    assert L.ctaug_warp_bspline_backward_workspace(od, g8) == m + rows * 3 * 512 * 8
+    assert L.ctaug_warp_bspline_backward_workspace(od, g8) == \
+        m + (rows + min(rows, 64)) * 3 * 512 * 8
     # controls closer than 2 voxels along z: the dense route (field, its gradient,
     # the B-spline adjoint's workspace)
     gz = (ctypes.c_int64 * 3)(8, 8, 60)

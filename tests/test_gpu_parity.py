@@ -444,7 +444,8 @@ def test_warp_bspline_backward_parity(in_dim, out_dim, grid, dtype, fused):
     G = (ctypes.c_int64 * 3)(*grid)
     L = ctaug._lib.load()
     m_bytes = ctaug.ops.warp_backward_workspace(out_dim)     # rows x 12 doubles
-    ws_fused = -(-m_bytes // 256) * 256 + (m_bytes // 96) * 3 * int(np.prod(grid)) * 8
+    rows = m_bytes // 96
+    ws_fused = -(-m_bytes // 256) * 256 + (rows + min(rows, 64)) * 3 * int(np.prod(grid)) * 8
     assert (int(L.ctaug_warp_bspline_backward_workspace(od, G)) == ws_fused) == fused
     g_img, g_M, g_c = ctaug.warp_bspline_backward(_t(img), M, _t(C), _t(g))
     r_img, r_M, r_u = oracle.warp_backward(img, M, g, disp=u, want_u=True)
