@@ -77,8 +77,8 @@ __device__ __forceinline__ float bs_profile(const float *__restrict__ ctrl, cons
 // 2^lz voxels along z, evaluated from the control grid: the row profiles of
 // the tile's rows over its z-control window are computed into s_prof (LDS,
 // 2^(lx+ly) * 3 * kSplineWindow floats), then each thread contracts z for its
-// own voxels z .. z + nvalid - 1 of row rr (x = x0 + (rr >> ly), y = y0 +
-// (rr & (2^ly - 1))).  A window of more than kSplineWindow controls (controls
+// own voxels z + k * zstep, k < nvalid, of row rr (x = x0 + (rr >> ly), y =
+// y0 + (rr & (2^ly - 1))).  A window of more than kSplineWindow controls (controls
 // closer than about 4 voxels along z) evaluates the profiles per voxel when
 // PER_VOXEL is set; without it the caller guarantees that every window fits.
 // Contains a workgroup barrier: every thread of the workgroup calls it.
@@ -88,7 +88,7 @@ template <int NT, bool PER_VOXEL = true>
 __device__ __forceinline__ void spline_tile_u(const float *__restrict__ ctrl, const BsplineGeom &B,
                                               int lx, int ly, int x0, int y0, int z0, int x1,
                                               int y1, int z1, int rr, int x, int y, int z,
-                                              int nvalid, bool mine, float *s_prof,
+                                              int zstep, int nvalid, bool mine, float *s_prof,
                                               float (&u)[3][4])
 {
     const int izl = bs_index(z0, B.inv_hz, B.gz);
@@ -114,7 +114,7 @@ __device__ __forceinline__ void spline_tile_u(const float *__restrict__ ctrl, co
                 break;
             int32_t iz;
             float tz, Bz[4];
-            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
+            bs_cell(z + k * zstep, B.inv_hz, B.gz, iz, tz);
             bs_basis(tz, Bz);
 #pragma unroll
             for (int comp = 0; comp < 3; ++comp) {
@@ -129,7 +129,7 @@ __device__ __forceinline__ void spline_tile_u(const float *__restrict__ ctrl, co
         for (int k = 0; k < nvalid; ++k) {
             int32_t iz;
             float tz, Bz[4];
-            bs_cell(z + k, B.inv_hz, B.gz, iz, tz);
+            bs_cell(z + k * zstep, B.inv_hz, B.gz, iz, tz);
             bs_basis(tz, Bz);
 #pragma unroll
             for (int comp = 0; comp < 3; ++comp) {

@@ -95,6 +95,39 @@ __device__ __forceinline__ float quad_sum(float v)
     return v;
 }
 
+// Fixed-point image adjoint.  A tile's contributions w_c * g are added into
+// 64-bit integer LDS accumulators (integer LDS atomics run at full rate where
+// FP32 ones do not, and integer sums do not depend on the order of the
+// additions): with gmax the tile's largest |g| and gmax < 2^e, each FP32
+// contribution v is scaled by S = 2^(52 - e) (exact) and rounded to the
+// nearest integer, so |v S| < 2^52 and, as the weights of a sample sum to 1,
+// every cell's sum over the tile's 1024 samples stays below 2^62.
+__device__ __forceinline__ long long to_fixed(float v, float S)
+{
+    const float x = rintf(v * S);
+    const float ax = fabsf(x);
+    const float hi = floorf(ax * 0x1p-32f);
+    const float lo = __builtin_fmaf(-hi, 0x1p32f, ax);   // exact: the low 32 bits of ax
+    const long long m = (long long)((unsigned long long)(unsigned)hi << 32 | (unsigned)lo);
+    return x < 0.0f ? -m : m;
+}
+
+__device__ __forceinline__ float block_max(float v, float *s)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmaxf(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float m = s[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w)
+        m = fmaxf(m, s[w]);
+    __syncthreads();
+    return m;
+}
+
 // Spline weight matrix of one tile axis: Wt[p][c] = B_{c - (i(p) - i(p0))}(t(p))
 // for the 2^lp voxels p0 + p <= p1 of the axis and the window of kSplineWindow
 // controls starting at i(p0); 0 elsewhere.  One entry per calling thread.
@@ -155,8 +188,8 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
     // z: the 4 lanes of a row hold its 16 voxels; butterfly sum over them
 #pragma unroll 1
     for (int c = 0; c < NW; ++c) {
-        const float *zc = Zw + (4 * zr) * NW + c;
-        const float w0 = zc[0], w1 = zc[NW], w2 = zc[2 * NW], w3 = zc[3 * NW];
+        const float *zc = Zw + zr * NW + c;    // voxel k of the run sits at z offset zr + 4k
+        const float w0 = zc[0], w1 = zc[4 * NW], w2 = zc[8 * NW], w3 = zc[12 * NW];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             float v = w0 * gu[0][i];
@@ -251,8 +284,11 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     }
 
     __shared__ int s_red[kThreads / 64][6];
+    __shared__ float s_gmax[kThreads / 64];
 
-    // this thread's run inside every tile
+    // this thread's run inside every tile: voxels z0 + zr + 4k, k = 0..3, of row
+    // (xr, yr).  Lanes next to each other take neighbouring z, so that the LDS
+    // accumulator updates of one instruction fall in different banks.
     const int zr = threadIdx.x & 3;
     const int yr = (threadIdx.x >> 2) & 7;
     const int xr = threadIdx.x >> 5;
@@ -263,9 +299,9 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         const int x0 = tx << TL.lx, y0 = ty << TL.ly, z0 = tz << TL.lz;
         const int x1 = min(x0 + (1 << TL.lx), J.ox) - 1, y1 = min(y0 + (1 << TL.ly), J.oy) - 1,
                   z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
-        const int x = x0 + xr, y = y0 + yr, z = z0 + 4 * zr;
+        const int x = x0 + xr, y = y0 + yr, z = z0 + zr;
         const bool run_ok = x <= x1 && y <= y1 && z <= z1;
-        const int nvalid = run_ok ? min(4, J.oz - z) : 0;
+        const int nvalid = run_ok ? min(4, (z1 - z) / 4 + 1) : 0;
         const int32_t v0 = run_ok ? (x * J.oy + y) * J.oz + z : 0;
         // coordinates, guard and upstream gradient of the run's voxels
         float qv[4][3], gpk[4];
@@ -273,7 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         float u[3][4];
         if (DISP == kDispSpline)
             spline_tile_u<kThreads, false>(J.ctrl, J.bs, TL.lx, TL.ly, x0, y0, z0, x1, y1, z1,
-                                    threadIdx.x >> 2, x, y, z, nvalid, run_ok, s_cells, u);
+                                           threadIdx.x >> 2, x, y, z, 4, nvalid, run_ok,
+                                           s_cells, u);
         {
             float rb[3];
             row_base(J.M, (float)x, (float)y, rb);
@@ -284,8 +321,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 qv[k][0] = qv[k][1] = qv[k][2] = 0.0f;
                 if (k >= nvalid)
                     continue;
-                const int32_t v = v0 + k;
-                const float zf = (float)(z + k);
+                const int32_t v = v0 + 4 * k;
+                const float zf = (float)(z + 4 * k);
                 float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
                       qz = coord(J.M, 2, rb, zf);
                 if (DISP == kDispField) {
@@ -330,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
             __syncthreads();
         }
         // per voxel of the run: LDS cell of corner (0,0,0), fractions, upstream gradient
-        int base[4];
+        int base[4], cx0[4];
         float tw[4][3], gk[4];
         bool live[4] = {false, false, false, false};
         float S[3] = {0.0f, 0.0f, 0.0f}, Sz[3] = {0.0f, 0.0f, 0.0f};
@@ -343,8 +380,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
             for (int k = 0; k < 4; ++k) {
                 if (k >= nvalid)
                     continue;
-                const int32_t v = v0 + k;
-                const float zf = (float)(z + k);
+                const int32_t v = v0 + 4 * k;
+                const float zf = (float)(z + 4 * k);
                 const float qx = qv[k][0], qy = qv[k][1], qz = qv[k][2];
                 const float gp = gpk[k];
                 float dV[3] = {0.0f, 0.0f, 0.0f};
@@ -372,6 +409,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                         if (g_img) {
                             live[k] = true;
                             base[k] = bs;
+                            cx0[k] = (int)fx - G.lo[0];
                             tw[k][0] = tt[0];
                             tw[k][1] = tt[1];
                             tw[k][2] = tt[2];
@@ -428,45 +466,91 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         if (lds) {                         // uniform: no barrier is skipped by part of the group
             __syncthreads();               // every corner read of the staged image is done
             if (g_img) {
-                // the footprint cells become FP32 accumulators of w_c * g
-                const int cells = G.e[0] * sxy;
-                for (int c = 4 * threadIdx.x; c < cells; c += 4 * kThreads)
-                    *reinterpret_cast<f32x4 *>(s_cells + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                __syncthreads();
+                float gm = 0.0f;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (!live[k])
-                        continue;
-                    const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
-                    const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
-                    const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int bb = 0; bb < 2; ++bb) {
-                            const float wxy = wx[a] * wy[bb];
-                            float *row = s_cells + base[k] + a * sxy + bb * pitch;
-                            atomicAdd(row, wxy * gz0);
-                            atomicAdd(row + 1, wxy * gz1);
-                        }
-                }
-                __syncthreads();
-                // flush: one global atomic per touched in-volume footprint cell
+                for (int k = 0; k < 4; ++k)
+                    if (live[k])
+                        gm = fmaxf(gm, fabsf(gk[k]));
+                gm = block_max(gm, s_gmax);
+                // x-planes of 64-bit accumulators that fit the footprint reservation
+                const int planes = (lds_cells >> 1) / sxy;
                 const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
-                for (int c = threadIdx.x; c < cells; c += kThreads) {
-                    const float v = s_cells[c];
-                    if (v == 0.0f)
-                        continue;
-                    const int row = div_small(c, pitch, rcp_pitch);
-                    const int cz = c - row * pitch;
-                    const int cx = div_small(row, ey, rcp_ey);
-                    const int cy = row - cx * ey;
-                    const int gx = G.lo[0] + cx, gy = G.lo[1] + cy, gz = G.lo[2] + cz;
-                    if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
-                        (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
-                        unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz, v);
+                if (gm > 0.0f && gm <= 0x1p126f && gm >= 0x1p-70f && planes > 0) {
+                    const int e = ilogbf(gm) + 1;          // gm < 2^e
+                    const float S = ldexpf(1.0f, 52 - e);
+                    const double rS = ldexp(1.0, e - 52);
+                    long long *s_acc = reinterpret_cast<long long *>(s_cells);
+                    for (int sx0 = 0; sx0 < G.e[0]; sx0 += planes) {   // uniform
+                        const int np = min(planes, G.e[0] - sx0);
+                        const int n = np * sxy;                        // a multiple of 4
+                        for (int c = 2 * threadIdx.x; c < n; c += 2 * kThreads)
+                            *reinterpret_cast<f32x4 *>(s_acc + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                        __syncthreads();
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (!live[k])
+                                continue;
+                            const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
+                            const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
+                            const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
+#pragma unroll
+                            for (int a = 0; a < 2; ++a) {
+                                const int px = cx0[k] + a - sx0;
+                                if ((unsigned)px >= (unsigned)np)
+                                    continue;
+#pragma unroll
+                                for (int bb = 0; bb < 2; ++bb) {
+                                    const float wxy = wx[a] * wy[bb];
+                                    unsigned long long *row = reinterpret_cast<unsigned long long *>(
+                                        s_acc + base[k] - cx0[k] * sxy + px * sxy + bb * pitch);
+                                    atomicAdd(row, (unsigned long long)to_fixed(wxy * gz0, S));
+                                    atomicAdd(row + 1, (unsigned long long)to_fixed(wxy * gz1, S));
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        // flush: one global atomic per touched in-volume footprint cell
+                        for (int c = threadIdx.x; c < n; c += kThreads) {
+                            const long long v = s_acc[c];
+                            if (v == 0)
+                                continue;
+                            const int row = div_small(c, pitch, rcp_pitch);
+                            const int cz = c - row * pitch;
+                            const int cx = div_small(row, ey, rcp_ey);
+                            const int cy = row - cx * ey;
+                            const int gx = G.lo[0] + sx0 + cx, gy = G.lo[1] + cy,
+                                      gz = G.lo[2] + cz;
+                            if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
+                                (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
+                                unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz,
+                                                (float)((double)v * rS));
+                        }
+                        __syncthreads();   // LDS is reused next
+                    }
+                } else if (gm != 0.0f) {
+                    // non-finite, tiny or huge gradients: FP32 global atomics per corner
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (!live[k])
+                            continue;
+                        const int rel = base[k] - cx0[k] * sxy;
+                        const int cy0 = rel / pitch, cz0 = rel - cy0 * pitch;
+                        const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
+                        const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
+                        const float gz[2] = {(1.0f - tw[k][2]) * gk[k], tw[k][2] * gk[k]};
+                        for (int a = 0; a < 2; ++a)
+                            for (int bb = 0; bb < 2; ++bb)
+                                for (int c = 0; c < 2; ++c) {
+                                    const int gx = G.lo[0] + cx0[k] + a, gy = G.lo[1] + cy0 + bb,
+                                              gz2 = G.lo[2] + cz0 + c;
+                                    if ((unsigned)gx < (unsigned)J.nx &&
+                                        (unsigned)gy < (unsigned)J.ny &&
+                                        (unsigned)gz2 < (unsigned)J.nz)
+                                        unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz2,
+                                                        wx[a] * wy[bb] * gz[c]);
+                                }
+                    }
                 }
-                __syncthreads();           // LDS is reused next
             }
         }
         if (want_ctrl)

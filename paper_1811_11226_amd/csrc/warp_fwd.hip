@@ -243,7 +243,7 @@ __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling
         float u[3][4];
         if (DISP == kDispSpline)
             spline_tile_u<kThreads>(J.ctrl, J.bs, TL.lx, TL.ly, x0, y0, z0, x1, y1, z1, rr, x, y,
-                                    z, nvalid, mine, reinterpret_cast<float *>(s_lds), u);
+                                    z, 1, nvalid, mine, reinterpret_cast<float *>(s_lds), u);
         RunQ Q;
         int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
         if (mine) {
