@@ -463,8 +463,12 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 acc[4 * i + 3] += (double)S[i];
             }
         }
-        if (lds) {                         // uniform: no barrier is skipped by part of the group
+        if (lds)                           // uniform: no barrier is skipped by part of the group
             __syncthreads();               // every corner read of the staged image is done
+        if (want_ctrl)                     // before the image scatter: gu dies here
+            ctrl_adjoint_tile(J.bs, x0, y0, z0, x1, y1, z1, threadIdx.x >> 2, zr, gu, s_cells,
+                              s_ctrl);
+        if (lds) {
             if (g_img) {
                 float gm = 0.0f;
 #pragma unroll
@@ -507,6 +511,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                                     atomicAdd(row + 1, (unsigned long long)to_fixed(wxy * gz1, S));
                                 }
                             }
+                            // one voxel's conversions at a time (register pressure)
+                            __builtin_amdgcn_sched_barrier(0);
                         }
                         __syncthreads();
                         // flush: one global atomic per touched in-volume footprint cell
@@ -553,9 +559,6 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 }
             }
         }
-        if (want_ctrl)
-            ctrl_adjoint_tile(J.bs, x0, y0, z0, x1, y1, z1, threadIdx.x >> 2, zr, gu, s_cells,
-                              s_ctrl);
     }
 
     if (want_ctrl)                         // the last tile ended with a barrier
