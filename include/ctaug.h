@@ -26,8 +26,9 @@
  *    call returns a nonzero ctaug_status and leaves every output untouched.
  *    No exception crosses the ABI and the library never prints.
  *  - The only calls that allocate device or pinned memory are
- *    ctaug_batch_plan_create (owned by the plan, freed by
- *    ctaug_batch_plan_destroy); compute calls take caller workspace.
+ *    ctaug_batch_plan_create and ctaug_pipeline_create (owned by the plan or
+ *    pipeline, freed by its destroy call); compute calls take caller
+ *    workspace.
  *  - Empty volumes (a zero dimension) are valid and make a call a no-op.
  *  - The sampling coordinate of output voxel p is, per axis i,
  *        q_i = fmaf(A_i2, z, fmaf(A_i1, y, fmaf(A_i0, x, b_i)))
@@ -401,6 +402,52 @@ ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *plan, const ctaug_tunin
 
 ctaug_status ctaug_batch_plan_get_tuning(const ctaug_batch_plan *plan, ctaug_tuning *out);
 ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *plan);
+
+/* ------------------------------------------------------------------------ */
+/* Host-to-device FIFO (Sec. "GPU-accelerated data augmentation": volumes    */
+/* are queued on the host while the GPU augments earlier ones, so that       */
+/* transfers overlap the warps)                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct ctaug_pipeline ctaug_pipeline;
+
+/* Create a FIFO of `depth` >= 2 slots of `slot_bytes` bytes each: pinned host
+ * buffers the caller fills, device buffers the warps read, a copy stream and
+ * a compute stream (default priority), and per-slot events.  Owned by the
+ * pipeline, freed by ctaug_pipeline_destroy.  Errors: EINVAL (depth < 2 or >
+ * 64, slot_bytes 0, null out), EHIP (allocation). */
+ctaug_status ctaug_pipeline_create(int32_t depth, size_t slot_bytes, ctaug_pipeline **out);
+
+/* Hand out the next slot's pinned host buffer (*host_slot, slot_bytes bytes)
+ * for the caller to fill with one volume (image, optionally labels, at any
+ * offsets).  Blocks the calling host thread until the warp that last read the
+ * slot has finished.  Errors: EINVAL (null argument, a slot already handed
+ * out and not submitted), EHIP. */
+ctaug_status ctaug_pipeline_acquire(ctaug_pipeline *p, void **host_slot);
+
+/* Queue the acquired slot: copy the bytes of img (and lbl) from the host
+ * slot to the device slot on the copy stream, then run the fused affine warp
+ * (as ctaug_warp_affine, same results bit for bit) on the compute stream once
+ * the copy has landed.  img->data / lbl->data are HOST pointers inside the
+ * acquired slot; img_out / lbl_out are device volumes owned by the caller,
+ * written asynchronously on the compute stream (ctaug_pipeline_sync, or an
+ * event on ctaug_pipeline_stream's stream, orders later work after them).
+ * Errors: as ctaug_warp_affine, plus EINVAL when no slot is acquired or an
+ * input does not lie inside it; on an error the slot stays acquired and
+ * nothing is queued, so a corrected submit may follow. */
+ctaug_status ctaug_pipeline_submit(ctaug_pipeline *p, const ctaug_vol *img_host,
+                                   const ctaug_vol *lbl_host, const float M[12], float fill,
+                                   int32_t label_fill, const ctaug_photo *photo,
+                                   ctaug_vol *img_out, ctaug_vol *lbl_out);
+
+/* The compute stream (hipStream_t as void*) the pipeline's warps run on. */
+ctaug_status ctaug_pipeline_stream(ctaug_pipeline *p, void **stream);
+
+/* Block until every submitted copy and warp has finished.  Errors: EINVAL, EHIP. */
+ctaug_status ctaug_pipeline_sync(ctaug_pipeline *p);
+
+/* Wait for outstanding work, then free every buffer, stream and event. */
+ctaug_status ctaug_pipeline_destroy(ctaug_pipeline *p);
 
 /* ------------------------------------------------------------------------ */
 /* Measurement helper                                                        */

@@ -87,6 +87,13 @@ SIGNATURES = {
     "ctaug_bspline_upsample": (_S, [_P, _PI64, _PI64, _P, _P]),
     "ctaug_bspline_adjoint_workspace": (ctypes.c_size_t, [_PI64, _PI64]),
     "ctaug_bspline_upsample_adjoint": (_S, [_P, _PI64, _PI64, _P, _P, ctypes.c_size_t, _P]),
+    "ctaug_pipeline_create": (_S, [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
+    "ctaug_pipeline_acquire": (_S, [_P, ctypes.POINTER(ctypes.c_void_p)]),
+    "ctaug_pipeline_submit": (_S, [_P, _PV, _PV, _PF, ctypes.c_float, ctypes.c_int32,
+                                   ctypes.POINTER(Photo), _PV, _PV]),
+    "ctaug_pipeline_stream": (_S, [_P, ctypes.POINTER(ctypes.c_void_p)]),
+    "ctaug_pipeline_sync": (_S, [_P]),
+    "ctaug_pipeline_destroy": (_S, [_P]),
     "ctaug_batch_plan_create": (_S, [ctypes.POINTER(Job), ctypes.c_int32,
                                      ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_void_p)]),
     "ctaug_batch_plan_update": (_S, [_P, ctypes.POINTER(Job)]),

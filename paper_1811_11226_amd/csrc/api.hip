@@ -1092,3 +1092,188 @@ extern "C" ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *p, const cta
         *best = cand[best_i];
     return st;
 }
+
+// ---------------------------------------------------------------------------
+// Host-to-device FIFO: pinned host slots filled by the caller, device slots
+// read by the warps, a copy stream and a compute stream.  Slot s is reused
+// only after the warp that read it has finished (event done[s]); the copy of
+// slot s+1 proceeds on the copy engine while the warp of slot s runs.
+// ---------------------------------------------------------------------------
+
+struct ctaug_pipeline {
+    int32_t depth = 0;
+    size_t slot_bytes = 0;
+    std::vector<void *> host;          // pinned (hipHostMalloc)
+    std::vector<void *> dev;
+    std::vector<hipEvent_t> copied;    // H2D of the slot's volume finished
+    std::vector<hipEvent_t> done;      // the warp reading the slot finished
+    std::vector<char> pending;         // done[] recorded and not yet waited for
+    hipStream_t copy = nullptr;
+    hipStream_t compute = nullptr;
+    int32_t next = 0;                  // slot the next acquire hands out
+    int32_t held = -1;                 // slot handed out and not yet submitted
+};
+
+namespace {
+
+void pipeline_free(ctaug_pipeline *p)
+{
+    if (p->copy)
+        (void)hipStreamSynchronize(p->copy);
+    if (p->compute)
+        (void)hipStreamSynchronize(p->compute);
+    for (void *h : p->host)
+        if (h)
+            (void)hipHostFree(h);
+    for (void *d : p->dev)
+        if (d)
+            (void)hipFree(d);
+    for (hipEvent_t e : p->copied)
+        if (e)
+            (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->done)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (p->copy)
+        (void)hipStreamDestroy(p->copy);
+    if (p->compute)
+        (void)hipStreamDestroy(p->compute);
+    delete p;
+}
+
+// Byte range of a volume's data inside [base, base + size), as an offset.
+bool slot_offset(const ctaug_vol *v, const void *base, size_t size, size_t &off, size_t &bytes)
+{
+    const size_t esz = v->dtype == CTAUG_F32 ? 4 : v->dtype == CTAUG_I16 ? 2 : 1;
+    bytes = (size_t)nelem(v->dim) * esz;
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base), d = reinterpret_cast<uintptr_t>(v->data);
+    if (bytes == 0)
+        return true;
+    if (d < b || d - b > size || bytes > size - (d - b))
+        return false;
+    off = (size_t)(d - b);
+    return true;
+}
+
+}  // namespace
+
+extern "C" ctaug_status ctaug_pipeline_create(int32_t depth, size_t slot_bytes,
+                                              ctaug_pipeline **out)
+{
+    if (!out || depth < 2 || depth > 64 || slot_bytes == 0)
+        return CTAUG_EINVAL;
+    ctaug_pipeline *p = new (std::nothrow) ctaug_pipeline();
+    if (!p)
+        return CTAUG_EINVAL;
+    p->depth = depth;
+    p->slot_bytes = slot_bytes;
+    p->host.assign(depth, nullptr);
+    p->dev.assign(depth, nullptr);
+    p->copied.assign(depth, nullptr);
+    p->done.assign(depth, nullptr);
+    p->pending.assign(depth, 0);
+    bool ok = hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&p->compute, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < depth; ++i)
+        ok = hipHostMalloc(&p->host[i], slot_bytes, hipHostMallocDefault) == hipSuccess &&
+             hipMalloc(&p->dev[i], slot_bytes) == hipSuccess &&
+             hipEventCreateWithFlags(&p->copied[i], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&p->done[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        pipeline_free(p);
+        return CTAUG_EHIP;
+    }
+    *out = p;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_pipeline_acquire(ctaug_pipeline *p, void **host_slot)
+{
+    if (!p || !host_slot || p->held >= 0)
+        return CTAUG_EINVAL;
+    const int32_t s = p->next;
+    if (p->pending[s]) {
+        if (hipEventSynchronize(p->done[s]) != hipSuccess)
+            return CTAUG_EHIP;
+        p->pending[s] = 0;
+    }
+    p->held = s;
+    *host_slot = p->host[s];
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_pipeline_submit(ctaug_pipeline *p, const ctaug_vol *img_host,
+                                              const ctaug_vol *lbl_host, const float M[12],
+                                              float fill, int32_t label_fill,
+                                              const ctaug_photo *photo, ctaug_vol *img_out,
+                                              ctaug_vol *lbl_out)
+{
+    if (!p || p->held < 0 || !img_host)
+        return CTAUG_EINVAL;
+    const int32_t s = p->held;
+    size_t io = 0, ib = 0, lo = 0, lb = 0;
+    if (!slot_offset(img_host, p->host[s], p->slot_bytes, io, ib))
+        return CTAUG_EINVAL;
+    if (lbl_host && !slot_offset(lbl_host, p->host[s], p->slot_bytes, lo, lb))
+        return CTAUG_EINVAL;
+    // the same volumes at the device slot's addresses
+    char *dbase = static_cast<char *>(p->dev[s]);
+    ctaug_vol img_dev = *img_host, lbl_dev{};
+    img_dev.data = ib ? dbase + io : nullptr;
+    if (lbl_host) {
+        lbl_dev = *lbl_host;
+        lbl_dev.data = lb ? dbase + lo : nullptr;
+    }
+    FwdJob J;
+    ctaug_status st = make_job(&img_dev, lbl_host ? &lbl_dev : nullptr, M, nullptr, false, fill,
+                               label_fill, photo, img_out, lbl_out, kDefaultTiling, J);
+    if (st != CTAUG_OK)
+        return st;
+    const char *hbase = static_cast<const char *>(p->host[s]);
+    hipError_t e = hipSuccess;
+    if (ib)
+        e = hipMemcpyAsync(dbase + io, hbase + io, ib, hipMemcpyHostToDevice, p->copy);
+    if (e == hipSuccess && lb)
+        e = hipMemcpyAsync(dbase + lo, hbase + lo, lb, hipMemcpyHostToDevice, p->copy);
+    if (e == hipSuccess)
+        e = hipEventRecord(p->copied[s], p->copy);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(p->compute, p->copied[s], 0);
+    if (e == hipSuccess && !empty(J))
+        e = launch_warp_single(J, kDefaultTiling, p->compute);
+    if (e == hipSuccess)
+        e = hipEventRecord(p->done[s], p->compute);
+    if (e != hipSuccess)
+        return CTAUG_EHIP;
+    p->pending[s] = 1;
+    p->held = -1;
+    p->next = (s + 1) % p->depth;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_pipeline_stream(ctaug_pipeline *p, void **stream)
+{
+    if (!p || !stream)
+        return CTAUG_EINVAL;
+    *stream = p->compute;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_pipeline_sync(ctaug_pipeline *p)
+{
+    if (!p)
+        return CTAUG_EINVAL;
+    if (hipStreamSynchronize(p->copy) != hipSuccess ||
+        hipStreamSynchronize(p->compute) != hipSuccess)
+        return CTAUG_EHIP;
+    std::fill(p->pending.begin(), p->pending.end(), 0);
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_pipeline_destroy(ctaug_pipeline *p)
+{
+    if (!p)
+        return CTAUG_EINVAL;
+    pipeline_free(p);
+    return CTAUG_OK;
+}

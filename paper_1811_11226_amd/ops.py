@@ -429,3 +429,100 @@ def gaussian_smooth(volume, sigma, out=None):
                                        ctypes.c_void_p(ws.data_ptr()), ws_bytes, _stream()),
                "ctaug_gaussian_smooth")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Host-to-device FIFO
+# ---------------------------------------------------------------------------
+
+_NP_DTYPES = {np.dtype(np.float32): CTAUG_F32, np.dtype(np.int16): CTAUG_I16,
+              np.dtype(np.int8): _lib.CTAUG_I8}
+
+
+def _host_vol(addr, arr):
+    v = _lib.Vol()
+    v.data = addr if arr.size else None
+    v.dtype = _NP_DTYPES[arr.dtype]
+    v.reserved = 0
+    for i in range(3):
+        v.dim[i] = arr.shape[i]
+    return v
+
+
+class Pipeline:
+    """Host-to-device FIFO over `depth` pinned slots of `slot_bytes` bytes:
+    put() copies a host volume (and labels) into the next pinned slot (the
+    producer's work), then queues its transfer and its fused affine warp; the
+    transfer of one volume overlaps the warps of earlier ones."""
+
+    def __init__(self, depth, slot_bytes):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().ctaug_pipeline_create(int(depth), int(slot_bytes), ctypes.byref(h)),
+                   "ctaug_pipeline_create")
+        self._h = h
+        self.slot_bytes = int(slot_bytes)
+
+    @staticmethod
+    def slot_bytes_for(img_shape, img_dtype=np.int16, labels=True):
+        n = int(np.prod(img_shape))
+        b = (n * np.dtype(img_dtype).itemsize + 255) // 256 * 256
+        return b + (n if labels else 0)
+
+    def acquire(self):
+        """Address of the next pinned host slot (blocks until it is free)."""
+        slot = ctypes.c_void_p()
+        _lib.check(_lib.load().ctaug_pipeline_acquire(self._h, ctypes.byref(slot)),
+                   "ctaug_pipeline_acquire")
+        return slot.value
+
+    def submit(self, img_addr, img_like, M, lbl_addr=None, lbl_like=None, fill=-1000.0,
+               label_fill=0, photo=None, out=None, lbl_out=None):
+        """Queue the acquired slot; img_like / lbl_like give dtype and shape of the
+        volumes at host addresses img_addr / lbl_addr inside the slot."""
+        vi = _host_vol(img_addr, img_like)
+        vl = _host_vol(lbl_addr, lbl_like) if lbl_like is not None else None
+        _require(out, "out", (torch.float32,))
+        vo = vol(out)
+        vlo = vol(lbl_out) if lbl_out is not None else None
+        st = _lib.load().ctaug_pipeline_submit(self._h, ctypes.byref(vi), _ref(vl), _M32(M),
+                                               float(fill), int(label_fill),
+                                               _ref(make_photo(photo)), ctypes.byref(vo),
+                                               _ref(vlo))
+        _lib.check(st, "ctaug_pipeline_submit")
+
+    def put(self, img, M, lbl=None, fill=-1000.0, label_fill=0, photo=None, out=None,
+            lbl_out=None):
+        """Copy numpy volumes into the next slot and queue them."""
+        img = np.ascontiguousarray(img)
+        off = (img.nbytes + 255) // 256 * 256
+        need = off + (lbl.nbytes if lbl is not None else 0)
+        if need > self.slot_bytes:
+            raise ValueError(f"volume needs {need} bytes, slots hold {self.slot_bytes}")
+        addr = self.acquire()
+        ctypes.memmove(addr, img.ctypes.data, img.nbytes)
+        lbl_addr = None
+        if lbl is not None:
+            lbl = np.ascontiguousarray(lbl)
+            lbl_addr = addr + off
+            ctypes.memmove(lbl_addr, lbl.ctypes.data, lbl.nbytes)
+        self.submit(addr, img, M, lbl_addr, lbl, fill, label_fill, photo, out, lbl_out)
+
+    def stream(self):
+        s = ctypes.c_void_p()
+        _lib.check(_lib.load().ctaug_pipeline_stream(self._h, ctypes.byref(s)),
+                   "ctaug_pipeline_stream")
+        return s.value
+
+    def sync(self):
+        _lib.check(_lib.load().ctaug_pipeline_sync(self._h), "ctaug_pipeline_sync")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.check(_lib.load().ctaug_pipeline_destroy(self._h), "ctaug_pipeline_destroy")
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

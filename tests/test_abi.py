@@ -320,6 +320,24 @@ def test_fused_bspline_backward_workspace_and_validation(L):
     assert call(gout=vol((64, 64, 64), I16)) == EDTYPE
 
 
+# -- host-to-device FIFO -------------------------------------------------------
+
+def test_pipeline_validation_before_any_hip_call(L):
+    h = ctypes.c_void_p()
+    assert L.ctaug_pipeline_create(1, 1 << 20, ctypes.byref(h)) == EINVAL
+    assert L.ctaug_pipeline_create(65, 1 << 20, ctypes.byref(h)) == EINVAL
+    assert L.ctaug_pipeline_create(2, 0, ctypes.byref(h)) == EINVAL
+    assert L.ctaug_pipeline_create(2, 1 << 20, None) == EINVAL
+    slot = ctypes.c_void_p()
+    assert L.ctaug_pipeline_acquire(None, ctypes.byref(slot)) == EINVAL
+    r = ctypes.byref
+    assert L.ctaug_pipeline_submit(None, r(vol((4, 4, 4), I16)), None, mat(), 0.0, 0, None,
+                                   r(vol((4, 4, 4))), None) == EINVAL
+    assert L.ctaug_pipeline_stream(None, ctypes.byref(slot)) == EINVAL
+    assert L.ctaug_pipeline_sync(None) == EINVAL
+    assert L.ctaug_pipeline_destroy(None) == EINVAL
+
+
 # -- batch plan ---------------------------------------------------------------
 
 def _job(in_dims=(8, 8, 8), out_dims=(4, 4, 4), dtype=I16):

@@ -654,6 +654,66 @@ def test_resampling_pipeline_parity():
 
 
 # ---------------------------------------------------------------------------
+# Host-to-device FIFO
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("depth", [2, 3])
+def test_pipeline_matches_direct_warps(depth):
+    """Volumes streamed from pinned host slots through the FIFO give the same
+    bits as ctaug_warp_affine on device copies, with slots reused several times."""
+    rng = np.random.default_rng(90 + depth)
+    shapes = [(40, 36, 28), (33, 30, 17), (48, 20, 44), (25, 25, 25), (40, 36, 28), (12, 50, 31),
+              (37, 29, 40)]
+    out_dim = (32, 28, 24)
+    cases = []
+    for i, shp in enumerate(shapes):
+        img, lbl = phantom_pair(shp, seed=300 + i)
+        if i % 2:
+            img = img.astype(np.float32)
+        prm = draw_affine_params(rng, AugmentRanges(), shp, out_dim)
+        _, M = ctaug.affine_matrix(prm, shp, out_dim)
+        ph = draw_photo(rng, AugmentRanges(), seed=7, volume_id=i) if i % 3 else None
+        cases.append((img, lbl if i != 4 else None, M, ph))
+    slot = max(ctaug.Pipeline.slot_bytes_for(c[0].shape, c[0].dtype) for c in cases)
+    outs = [torch.empty(out_dim, dtype=torch.float32, device=DEV) for _ in cases]
+    louts = [torch.empty(out_dim, dtype=torch.int8, device=DEV) for _ in cases]
+    with ctaug.Pipeline(depth, slot) as pipe:
+        for (img, lbl, M, ph), o, lo in zip(cases, outs, louts):
+            pipe.put(img, M, lbl=lbl, photo=ph, out=o, lbl_out=lo if lbl is not None else None)
+        pipe.sync()
+    for (img, lbl, M, ph), o, lo in zip(cases, outs, louts):
+        ref, lref = ctaug.warp_affine(_t(img), M, lbl=_t(lbl) if lbl is not None else None,
+                                      photo=ph, out_dim=out_dim)
+        assert np.array_equal(_np(o).view(np.uint32), _np(ref).view(np.uint32))
+        if lbl is not None:
+            assert np.array_equal(_np(lo), _np(lref))
+
+
+def test_pipeline_rejects_inputs_outside_the_slot():
+    L = ctaug._lib.load()
+    with ctaug.Pipeline(2, 1 << 16) as pipe:
+        img = np.zeros((8, 8, 8), np.int16)
+        out = torch.empty((8, 8, 8), dtype=torch.float32, device=DEV)
+        vo = ctaug.ops.vol(out)
+        M_np = np.eye(3, 4).ravel()
+        M = ctaug.ops._M32(M_np)
+        vi = ctaug.ops._host_vol(img.ctypes.data, img)       # not a slot address
+        assert L.ctaug_pipeline_submit(pipe._h, ctypes.byref(vi), None, M, 0.0, 0, None,
+                                       ctypes.byref(vo), None) == 1   # nothing acquired
+        addr = pipe.acquire()
+        assert L.ctaug_pipeline_submit(pipe._h, ctypes.byref(vi), None, M, 0.0, 0, None,
+                                       ctypes.byref(vo), None) == 1   # outside the slot
+        big = np.zeros((64, 32, 17), np.int16)                       # 69632 bytes > slot
+        vb = ctaug.ops._host_vol(addr, big)
+        assert L.ctaug_pipeline_submit(pipe._h, ctypes.byref(vb), None, M, 0.0, 0, None,
+                                       ctypes.byref(vo), None) == 1
+        ctypes.memmove(addr, img.ctypes.data, img.nbytes)          # the slot stays acquired
+        pipe.submit(addr, img, M_np, out=out)
+        pipe.sync()
+        assert not _np(out).any()
+
+
+# ---------------------------------------------------------------------------
 # Batched persistent launch and HIP graph replay
 # ---------------------------------------------------------------------------
 
