@@ -76,13 +76,17 @@ __device__ __forceinline__ float bs_profile(const float *__restrict__ ctrl, cons
 // Displacement of one thread's run of a tile of 2^lx x 2^ly rows (x, y) by
 // 2^lz voxels along z, evaluated from the control grid: the row profiles of
 // the tile's rows over its z-control window are computed into s_prof (LDS,
-// 2^(lx+ly) * 3 * kSplineWindow floats), then each thread contracts z for its
+// up to 64 rows; 64 * 3 * kSplineWindow floats, plus the control window and
+// the y contraction, 4 * 3 * 64 * kSplineWindow floats in all, when the tile
+// touches at most kSplineWindow controls along x and y), then each thread contracts z for its
 // own voxels z + k * zstep, k < nvalid, of row rr (x = x0 + (rr >> ly), y =
 // y0 + (rr & (2^ly - 1))).  A window of more than kSplineWindow controls (controls
 // closer than about 4 voxels along z) evaluates the profiles per voxel when
 // PER_VOXEL is set; without it the caller guarantees that every window fits.
 // Contains a workgroup barrier: every thread of the workgroup calls it.
 constexpr int kSplineWindow = 8;
+constexpr int kSplineTileLdsFloats = 3 * 64 * kSplineWindow + 3 * kSplineWindow * kSplineWindow *
+                                     kSplineWindow + kSplineWindow * 8 * 3 * kSplineWindow;
 
 template <int NT, bool PER_VOXEL = true>
 __device__ __forceinline__ void spline_tile_u(const float *__restrict__ ctrl, const BsplineGeom &B,
@@ -96,13 +100,67 @@ __device__ __forceinline__ void spline_tile_u(const float *__restrict__ ctrl, co
     if (!PER_VOXEL || ncz <= kSplineWindow) {
         const int per_row = 3 * ncz;
         const int nent = per_row << (lx + ly);
-        for (int e = threadIdx.x; e < nent; e += NT) {
-            const int row = e / per_row;
-            const int rem = e - row * per_row;
-            const int comp = rem / ncz, c = rem - comp * ncz;
-            const int px = min(x0 + (row >> ly), x1);
-            const int py = min(y0 + (row & ((1 << ly) - 1)), y1);
-            s_prof[e] = bs_profile(ctrl, B, comp, px, py, izl + c);
+        const int ixl = bs_index(x0, B.inv_hx, B.gx), iyl = bs_index(y0, B.inv_hy, B.gy);
+        const int ncx = bs_index(x1, B.inv_hx, B.gx) - ixl + 4;
+        const int ncy = bs_index(y1, B.inv_hy, B.gy) - iyl + 4;
+        if (ncx <= kSplineWindow && ncy <= kSplineWindow) {
+            // separable, from the tile's control window staged in LDS: the same
+            // fmaf chains as bs_profile, sharing the y contraction of a control
+            // column among the rows of one y
+            float *Wc = s_prof + kSplineWindow * 3 * 64;                   // [3][ncx][ncy][ncz]
+            float *S = Wc + 3 * kSplineWindow * kSplineWindow * kSplineWindow;  // [ncx][ny][3][ncz]
+            const int ny = 1 << ly;
+            const int64_t gstride = (int64_t)B.gx * B.gy * B.gz;
+            const int nw = 3 * ncx * ncy * ncz;
+            for (int e = threadIdx.x; e < nw; e += NT) {
+                const int c = e % ncz, r1 = e / ncz;
+                const int b = r1 % ncy, r2 = r1 / ncy;
+                const int a = r2 % ncx, comp = r2 / ncx;
+                Wc[e] = ctrl[comp * gstride + ((int64_t)(ixl + a) * B.gy + (iyl + b)) * B.gz +
+                             izl + c];
+            }
+            __syncthreads();
+            const int ns = ncx * ny * per_row;
+            for (int e = threadIdx.x; e < ns; e += NT) {
+                const int cc = e % per_row, r1 = e / per_row;
+                const int yr = r1 % ny, a = r1 / ny;
+                const int comp = cc / ncz, c = cc - comp * ncz;
+                int32_t iy;
+                float ty, By[4];
+                bs_cell(min(y0 + yr, y1), B.inv_hy, B.gy, iy, ty);
+                bs_basis(ty, By);
+                const float *w = Wc + ((comp * ncx + a) * ncy + (iy - iyl)) * ncz + c;
+                float sa = 0.0f;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb)
+                    sa = __builtin_fmaf(By[bb], w[bb * ncz], sa);
+                S[e] = sa;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < nent; e += NT) {
+                const int row = e / per_row;
+                const int cc = e - row * per_row;
+                const int yr = row & (ny - 1);
+                int32_t ix;
+                float tx, Bx[4];
+                bs_cell(min(x0 + (row >> ly), x1), B.inv_hx, B.gx, ix, tx);
+                bs_basis(tx, Bx);
+                const float *sp = S + ((ix - ixl) * ny + yr) * per_row + cc;
+                float sv = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    sv = __builtin_fmaf(Bx[a], sp[a * ny * per_row], sv);
+                s_prof[e] = sv;
+            }
+        } else {
+            for (int e = threadIdx.x; e < nent; e += NT) {
+                const int row = e / per_row;
+                const int rem = e - row * per_row;
+                const int comp = rem / ncz, c = rem - comp * ncz;
+                const int px = min(x0 + (row >> ly), x1);
+                const int py = min(y0 + (row & ((1 << ly) - 1)), y1);
+                s_prof[e] = bs_profile(ctrl, B, comp, px, py, izl + c);
+            }
         }
         __syncthreads();
         if (!mine)

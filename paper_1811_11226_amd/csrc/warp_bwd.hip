@@ -85,6 +85,7 @@ __device__ __forceinline__ void cell_gradient(const float K[8], const float tt[3
 constexpr int32_t kCtrlMaxEntries = 2048;
 constexpr int32_t kSplineBwdCells = kBwdLdsCells - kCtrlMaxEntries;
 constexpr int32_t kCtrlRowGroups = 64;
+static_assert(kSplineTileLdsFloats <= kSplineBwdCells, "the B-spline scratch fits the reservation");
 
 // v + (v of the lane at quad position q ^ 1), then ^ 2: sum over the 4 lanes
 // of a quad, in the same order on every lane (DPP quad permutes, no LDS).

@@ -449,8 +449,8 @@ static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32
 constexpr Tiling kDispTiling = {3, 3, 4};
 constexpr int32_t kDispLdsCells = 10224;
 static_assert(1 << (3 + 3 + 4 - 2) == kThreads, "one run of a displacement tile per thread");
-static_assert(3 * kDispLdsCells >= 64 * 3 * kSplineWindow * (int32_t)sizeof(float),
-              "the B-spline row profiles of a tile fit its smallest footprint reservation");
+static_assert(3 * kDispLdsCells >= kSplineTileLdsFloats * (int32_t)sizeof(float),
+              "the B-spline scratch of a tile fits its smallest footprint reservation");
 
 hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s)
 {
