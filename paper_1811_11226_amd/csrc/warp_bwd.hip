@@ -28,6 +28,8 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 namespace ctaug {
 
@@ -700,17 +702,58 @@ bool bwd_ctrl_fused(const BsplineGeom &B)
            max_window(B.oy, kBwdTiling.ly, B.inv_hy, B.gy) <= kSplineWindow;
 }
 
-template <int DISP>
-static void launch_bwd_t(const FwdJob &J, int grid, size_t lds, hipStream_t s, const float *g,
-                         float *g_img, float *g_disp, double *part, double *ctrl_part, int nt,
-                         int32_t cells)
+// Workgroups the device keeps resident for kernel fn with lds bytes of dynamic
+// LDS (occupancy x compute units), cached per device, kernel and LDS size.
+static int resident_groups(const void *fn, size_t lds)
 {
+    struct Entry {
+        int dev;
+        const void *fn;
+        size_t lds;
+        int groups;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry &e : cache)
+        if (e.dev == dev && e.fn == fn && e.lds == lds)
+            return e.groups;
+    int cus = 0, occ = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, lds) != hipSuccess)
+        return 0;
+    cache.push_back({dev, fn, lds, cus * occ});
+    return cus * occ;
+}
+
+// Persistent grid: at most one wave of resident workgroups (a multiple of 8,
+// for the XCD-contiguous tile ranges), at most the workspace's rows.
+static int bwd_launch_grid(const void *fn, size_t lds, int64_t ntiles)
+{
+    const int64_t rows = bwd_grid(ntiles);
+    const int resident = resident_groups(fn, lds) & ~7;
+    return (int)(resident >= 8 ? std::min<int64_t>(rows, resident) : rows);
+}
+
+template <int DISP>
+static int launch_bwd_t(const FwdJob &J, int64_t ntiles, size_t lds, hipStream_t s,
+                        const float *g, float *g_img, float *g_disp, double *part,
+                        double *ctrl_part, int32_t cells)
+{
+    const void *fn = J.dtype == kI16 ? reinterpret_cast<const void *>(&k_warp_bwd<int16_t, DISP>)
+                                     : reinterpret_cast<const void *>(&k_warp_bwd<float, DISP>);
+    const int grid = bwd_launch_grid(fn, lds, ntiles);
+    const int nt = (int)ntiles;
     if (J.dtype == kI16)
         hipLaunchKernelGGL((k_warp_bwd<int16_t, DISP>), dim3(grid), dim3(kThreads), lds, s, J, g,
                            g_img, g_disp, part, ctrl_part, nt, cells);
     else
         hipLaunchKernelGGL((k_warp_bwd<float, DISP>), dim3(grid), dim3(kThreads), lds, s, J, g,
                            g_img, g_disp, part, ctrl_part, nt, cells);
+    return grid;
 }
 
 hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float *g_disp,
@@ -735,7 +778,6 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
         }
         return hipSuccess;
     }
-    const int grid = (int)bwd_grid(ntiles);
     // LDS cells sized for the largest footprint of any tile (a displacement has
     // no a-priori bound: the full reservation, used when a tile fits it)
     const bool displaced = J.disp || J.ctrl;
@@ -746,13 +788,13 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
     const size_t lds = (size_t)(J.ctrl ? kBwdLdsCells : cells) * sizeof(float);
     double *part = g_M ? partials : nullptr;
     double *cpart = g_ctrl ? ctrl_part : nullptr;
-    const int nt = (int)ntiles;
+    int grid;
     if (J.ctrl)
-        launch_bwd_t<kDispSpline>(J, grid, lds, s, g, g_img, g_disp, part, cpart, nt, cells);
+        grid = launch_bwd_t<kDispSpline>(J, ntiles, lds, s, g, g_img, g_disp, part, cpart, cells);
     else if (J.disp)
-        launch_bwd_t<kDispField>(J, grid, lds, s, g, g_img, g_disp, part, nullptr, nt, cells);
+        grid = launch_bwd_t<kDispField>(J, ntiles, lds, s, g, g_img, g_disp, part, nullptr, cells);
     else
-        launch_bwd_t<kDispNone>(J, grid, lds, s, g, g_img, nullptr, part, nullptr, nt, cells);
+        grid = launch_bwd_t<kDispNone>(J, ntiles, lds, s, g, g_img, nullptr, part, nullptr, cells);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
