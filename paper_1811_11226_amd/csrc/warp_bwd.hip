@@ -102,17 +102,16 @@ __device__ __forceinline__ float quad_sum(float v)
 // 64-bit integer LDS accumulators (integer LDS atomics run at full rate where
 // FP32 ones do not, and integer sums do not depend on the order of the
 // additions): with gmax the tile's largest |g| and gmax < 2^e, each FP32
-// contribution v is scaled by S = 2^(52 - e) (exact) and rounded to the
-// nearest integer, so |v S| < 2^52 and, as the weights of a sample sum to 1,
-// every cell's sum over the tile's 1024 samples stays below 2^62.
-__device__ __forceinline__ long long to_fixed(float v, float S)
+// contribution v is scaled by S = 2^(50 - e) (exact) and rounded to the
+// nearest integer (ties to even), so |v S| < 2^50 and, as the weights of a
+// sample sum to 1, every cell's sum over the tile's 1024 samples stays below
+// 2^60.  The rounding adds 1.5 * 2^52 in FP64, which leaves the integer in
+// the low mantissa bits: two integer operations recover it.
+__device__ __forceinline__ long long to_fixed(float v, double S)
 {
-    const float x = rintf(v * S);
-    const float ax = fabsf(x);
-    const float hi = floorf(ax * 0x1p-32f);
-    const float lo = __builtin_fmaf(-hi, 0x1p32f, ax);   // exact: the low 32 bits of ax
-    const long long m = (long long)((unsigned long long)(unsigned)hi << 32 | (unsigned)lo);
-    return x < 0.0f ? -m : m;
+    constexpr double kMagic = 0x1.8p52;
+    const double d = __builtin_fma((double)v, S, kMagic);
+    return __double_as_longlong(d) - __double_as_longlong(kMagic);
 }
 
 __device__ __forceinline__ float block_max(float v, float *s)
@@ -482,10 +481,10 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 // x-planes of 64-bit accumulators that fit the footprint reservation
                 const int planes = (lds_cells >> 1) / sxy;
                 const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
-                if (gm > 0.0f && gm <= 0x1p126f && gm >= 0x1p-70f && planes > 0) {
+                if (gm > 0.0f && gm <= 3.40282347e38f && planes > 0) {
                     const int e = ilogbf(gm) + 1;          // gm < 2^e
-                    const float S = ldexpf(1.0f, 52 - e);
-                    const double rS = ldexp(1.0, e - 52);
+                    const double S = ldexp(1.0, 50 - e);
+                    const double rS = ldexp(1.0, e - 50);
                     long long *s_acc = reinterpret_cast<long long *>(s_cells);
                     for (int sx0 = 0; sx0 < G.e[0]; sx0 += planes) {   // uniform
                         const int np = min(planes, G.e[0] - sx0);
@@ -537,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                         __syncthreads();   // LDS is reused next
                     }
                 } else if (gm != 0.0f) {
-                    // non-finite, tiny or huge gradients: FP32 global atomics per corner
+                    // non-finite gradients: FP32 global atomics per corner
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         if (!live[k])

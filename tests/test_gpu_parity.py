@@ -506,6 +506,29 @@ def test_affine_backward_parity(dims, dtype):
     assert_grad(_np(g_M), r_M, "g_M")
 
 
+@pytest.mark.parametrize("gscale,outliers", [(1e30, 0.0), (1e-30, 0.0), (1.0, 1e-12),
+                                             (1e-36, 0.0)])
+def test_affine_backward_gradient_magnitudes(gscale, outliers):
+    """The image adjoint sums a tile in 64-bit fixed point scaled by the tile's
+    largest |g|: huge gradients, tiny ones (down to FP32 subnormal products),
+    and a few normal values among 1e-12 ones (rounded at 2^-51 of the tile
+    maximum), against the oracle."""
+    rng = np.random.default_rng(int(abs(np.log10(gscale))) + 3)
+    dims = (40, 36, 44)
+    img, _ = phantom_pair(dims, seed=25)
+    img = img.astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    g = rng.standard_normal(dims) * gscale
+    if outliers:
+        g = np.where(rng.random(dims) < 0.01, g, g * outliers)
+    g = g.astype(np.float32)
+    g_img, g_M = ctaug.warp_affine_backward(_t(img), M, _t(g))
+    r_img, r_M, _ = oracle.warp_backward(img, M, g)
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
+
+
 @pytest.mark.parametrize("in_dim,out_dim,scale,dtype", [
     ((264, 128, 64), (264, 128, 64), (0.8, 1.2), np.float32),   # > 2048 tiles: strided WGs
     ((120, 100, 80), (30, 25, 20), (3.5, 4.0), np.int16),       # footprints beyond LDS
