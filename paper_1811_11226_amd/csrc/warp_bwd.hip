@@ -278,6 +278,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     // LDS after the footprint reservation
     const bool want_ctrl = DISP == kDispSpline && ctrl_part != nullptr;
     const int32_t nctrl = 3 * J.bs.gx * J.bs.gy * J.bs.gz;
+    // dV/dq (and so the staged corner values) is needed by every output but grad_img
+    const bool need_dv = partials != nullptr || g_disp != nullptr || want_ctrl;
     float *s_ctrl = s_cells + lds_cells;
     if (want_ctrl) {
         for (int e = threadIdx.x; e < nctrl; e += kThreads)
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         }
         const bool lds = G.lds;
         const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
-        if (lds) {
+        if (lds && need_dv) {              // the image adjoint alone needs no corner values
             stage_footprint<T, float>(J, src, G, s_cells, nullptr);
             __syncthreads();
         }
@@ -396,18 +398,20 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                                                       (uint32_t)((int)fy - G.lo[1]),
                                                   (uint32_t)pitch) +
                                        ((int)fz - G.lo[2]);
-                        K[0] = s_cells[bs];
-                        K[1] = s_cells[bs + 1];
-                        K[2] = s_cells[bs + pitch];
-                        K[3] = s_cells[bs + pitch + 1];
-                        K[4] = s_cells[bs + sxy];
-                        K[5] = s_cells[bs + sxy + 1];
-                        K[6] = s_cells[bs + sxy + pitch];
-                        K[7] = s_cells[bs + sxy + pitch + 1];
                         tt[0] = qx - fx;
                         tt[1] = qy - fy;
                         tt[2] = qz - fz;
-                        cell_gradient(K, tt, dV);
+                        if (need_dv) {
+                            K[0] = s_cells[bs];
+                            K[1] = s_cells[bs + 1];
+                            K[2] = s_cells[bs + pitch];
+                            K[3] = s_cells[bs + pitch + 1];
+                            K[4] = s_cells[bs + sxy];
+                            K[5] = s_cells[bs + sxy + 1];
+                            K[6] = s_cells[bs + sxy + pitch];
+                            K[7] = s_cells[bs + sxy + pitch + 1];
+                            cell_gradient(K, tt, dV);
+                        }
                         if (g_img) {
                             live[k] = true;
                             base[k] = bs;

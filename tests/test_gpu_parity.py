@@ -504,6 +504,10 @@ def test_affine_backward_parity(dims, dtype):
     r_img, r_M, _ = oracle.warp_backward(img, M, g)
     assert_grad(_np(g_img), r_img, "g_img")
     assert_grad(_np(g_M), r_M, "g_M")
+    # the image adjoint alone (no staged corner values)
+    g_img2, none = ctaug.warp_affine_backward(_t(img.astype(dtype)), M, _t(g), want_M=False)
+    assert none is None
+    assert_grad(_np(g_img2), r_img, "g_img alone")
 
 
 @pytest.mark.parametrize("gscale,outliers", [(1e30, 0.0), (1e-30, 0.0), (1.0, 1e-12),
@@ -607,6 +611,36 @@ def test_displacement_backward_parity(amp, dims, dtype):
     assert_grad(_np(g_img), r_img, "g_img")
     assert_grad(_np(g_M), r_M, "g_M")
     assert_grad(_np(g_disp), r_u, "g_disp")
+
+
+def test_autograd_affine_with_photometrics():
+    """gain, offset, noise and occlusion pass gain * grad_out (zero on the
+    occluded slab) to the warp adjoint; the forward output matches the oracle."""
+    from paper_1811_11226_amd import autograd as ag
+    rng = np.random.default_rng(34)
+    dims = (22, 26, 30)
+    img_np, _ = phantom_pair(dims, seed=6)
+    img_np = img_np.astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M32 = ctaug.affine_matrix(prm, dims, dims)
+    ph = draw_photo(rng, AugmentRanges(window=False, occlusion=8.0), seed=3, volume_id=1,
+                    out_z=dims[2])
+    assert ph.occlude
+    g = rng.standard_normal(dims).astype(np.float32)
+    img = _t(img_np).requires_grad_(True)
+    M = torch.tensor(M32.astype(np.float64), requires_grad=True)
+    out = ag.warp_affine(img, M, photo=ph)
+    ref, _ = oracle.warp(img_np, M32, dims, photo=ph)
+    assert_intensity(_np(out), ref, windowed=False, what="autograd forward")
+    (out * _t(g)).sum().backward()
+    z = np.arange(dims[2], dtype=np.float32)
+    keep = (z < np.float32(ph.occ_lo)) | (z > np.float32(ph.occ_hi))
+    g_eff = (g.astype(np.float64) * float(np.float32(ph.gain)) * keep).astype(np.float32)
+    r_img, r_M, _ = oracle.warp_backward(img_np, M32, g_eff)
+    assert_grad(_np(img.grad), r_img, "g_img")
+    assert_grad(M.grad.numpy(), r_M, "g_M")
+    with pytest.raises(ValueError):
+        ag.warp_affine(img, M, photo=draw_photo(rng, AugmentRanges(), seed=1, volume_id=0))
 
 
 def test_autograd_affine_and_nonrigid_chain():
