@@ -368,8 +368,8 @@ def run_c4(dev, stream, reps):
     fb_ms = time_loop(lambda: (fwd(), bwd()), reps, stream)
     nv = sum(o.numel() for o in outs)
     plan.close()
-    return {"workload": "8 x 128^3 f32 affine warp; backward to image (FP32 atomics, incl. zeroing)"
-                        " and to the 12 affine params (FP64 reduction)",
+    return {"workload": "8 x 128^3 f32 affine warp; backward to image (tile sums in fixed point, "
+                        "incl. zeroing) and to the 12 affine params (FP64 reduction)",
             "fwd_ms": round(f_ms, 4), "fwd_bwd_ms": round(fb_ms, 4),
             "fwd_gvoxel_s": round(nv / f_ms / 1e6, 2), "fwd_bwd_gvoxel_s": round(nv / fb_ms / 1e6, 2),
             "fwd_bwd_over_fwd": round(fb_ms / f_ms, 3)}

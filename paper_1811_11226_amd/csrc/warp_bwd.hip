@@ -1,26 +1,26 @@
 // warp_bwd.hip -- adjoint kernels of the warp (gfx950).
 //
-// For every output voxel the forward coordinate and cell are recomputed; the
-// eight corner values (fill substituted outside the volume) give the
-// derivative of the trilinear interpolant on that cell, dV/dq.  Then
-//   grad_img[c] += w_c * g          affine warps: FP32 atomics into LDS
-//                                   accumulators over the tile's input
-//                                   footprint, then one global FP32 atomic
-//                                   per touched cell (8x fewer than per corner);
-//                                   displacement warps (no footprint bound):
-//                                   global FP32 atomics per corner
+// Persistent workgroups over 8 x 8 x 16 output tiles.  For every output voxel
+// the forward coordinate and cell are recomputed; the eight corner values
+// (staged in LDS, fill substituted outside the volume) give the derivative of
+// the trilinear interpolant on that cell, dV/dq.  Then
+//   grad_img[c] += w_c * g          summed per tile in 64-bit fixed point in
+//                                   LDS (integer atomics, order-independent),
+//                                   then one global FP32 atomic per touched
+//                                   cell; tiles whose footprint exceeds the
+//                                   reservation, or with non-finite g, add
+//                                   per corner with global FP32 atomics
 //   grad_disp[i](p) = g * dV/dq_i   coalesced SoA stores
 //   grad_ctrl                        B-spline warps evaluated from a control
 //                                   grid: the tile's g dV/dq is contracted
 //                                   with the spline weights along z, y and x
-//                                   in LDS and added to FP64 accumulators that
-//                                   each thread keeps for its own control
-//                                   entries; one row per workgroup, summed by
-//                                   a second kernel in a fixed order
-//   per-tile partial of grad_M[i][j] = sum g dV/dq_i [x,y,z,1]_j, reduced in
-//   FP64 inside the workgroup in a fixed order and written to workspace slot
-//   (tile); a second kernel sums the slots in a fixed order.  grad_M is
-//   therefore deterministic; grad_img is not (atomic order).
+//                                   in LDS and added to the workgroup's LDS
+//                                   accumulators of the control entries; one
+//                                   row per workgroup, summed in a fixed order
+//   grad_M[i][j] = sum g dV/dq_i [x,y,z,1]_j, FP64 per thread, reduced in the
+//   workgroup and then across workgroups in a fixed order.
+// grad_M and grad_ctrl are deterministic for a given device; grad_img is
+// deterministic within a tile, and tiles meet in FP32 atomics.
 #include "device_common.h"
 #include "launch.h"
 #include "tile_geom.h"
