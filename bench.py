@@ -254,8 +254,11 @@ def run_c3(args, dev):
             sets[i % n_sets].plan.run()
             b.record(stream)
     torch.cuda.synchronize()
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    log(f"c3: fused batched kernel {kern_ms:.4f} ms per launch")
+    kts = np.array([a.elapsed_time(b) for a, b in evs])
+    kern_ms = float(np.mean(kts))
+    kern_pct = [float(np.percentile(kts, q)) for q in (10, 50, 90)]
+    log(f"c3: fused batched kernel {kern_ms:.4f} ms per launch (p10/p50/p90 "
+        f"{kern_pct[0]:.4f}/{kern_pct[1]:.4f}/{kern_pct[2]:.4f})")
 
     # correctness spot check of the last kernel-only launch against single calls
     s = sets[(args.steps - 1) % n_sets]
@@ -287,7 +290,8 @@ def run_c3(args, dev):
     log(f"c3: algorithmic bytes per launch {alg_bytes / 1e6:.1f} MB "
         f"(mean touched fraction f = {np.mean(touched):.3f}; {time.time() - t0:.1f} s)")
     log(f"c3: algorithmic lane-ops per launch {alg_ops / 1e9:.3f} G")
-    return dict(sets=sets, step_ms=step_ms, kern_ms=kern_ms, alg_bytes=alg_bytes, alg_ops=alg_ops,
+    return dict(sets=sets, step_ms=step_ms, kern_ms=kern_ms, kern_pct=kern_pct,
+                alg_bytes=alg_bytes, alg_ops=alg_ops,
                 tuning=best, tune_ms=times, voxels=sets[0].voxels(), stream=stream)
 
 
@@ -441,6 +445,49 @@ def run_c5(dev, stream, reps):
             "fwd_gvoxel_s": round(nv / f_ms / 1e6, 2), "fwd_bwd_gvoxel_s": round(nv / fb_ms / 1e6, 2),
             "fwd_bwd_over_fwd": round(fb_ms / f_ms, 3),
             "dense_field_fwd_ms": round(fd_ms, 4), "dense_field_fwd_bwd_ms": round(fbd_ms, 4)}
+
+
+def run_warp_only(sets, dev, stream, reps=30):
+    """The 16-volume batches with the photometric chain and the labels off: the
+    pure trilinear gather, whose bound is HBM (algorithmic bytes: 4 per output
+    voxel written, 2 per touched int16 input voxel read).  The three input sets
+    rotate, as in the headline measurement."""
+    import numpy as np
+    import torch
+
+    import paper_1811_11226_amd as ctaug
+    plans, nbytes = [], []
+    nv = C3_OUT[0] * C3_OUT[1] * C3_OUT[2]
+    for cs in sets:
+        jobs = [ctaug.make_job(cs.imgs[k], cs.pool[0][k][0], cs.outs[k], fill=j.fill)
+                for k, j in enumerate(cs.jobs)]
+        plans.append(ctaug.BatchPlan(jobs, tile=C3_TUNING[0], wg_per_cu=C3_TUNING[1],
+                                     lds_cells=C3_TUNING[2], lds_format=C3_TUNING[3]))
+        b = 0
+        for k, j in enumerate(cs.jobs):
+            ti, _, _ = touched_counts(j.in_dim, C3_OUT, cs.pool[0][k][0], dev)
+            b += nv * 4 + ti * 2
+        nbytes.append(b)
+    with torch.cuda.stream(stream):
+        for p in plans:
+            p.launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    with torch.cuda.stream(stream):
+        for i, (a, b) in enumerate(evs):
+            a.record(stream)
+            plans[i % len(plans)].run()
+            b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    for p in plans:
+        p.close()
+    b = float(np.mean(nbytes))
+    gbs = b / ms / 1e6
+    return {"workload": "the 16-volume batches, trilinear warp only (no labels, no photometrics)",
+            "kernel_ms": round(ms, 4), "gvoxel_s": round(sets[0].voxels() / ms / 1e6, 2),
+            "alg_bytes": int(b), "alg_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def run_fifo(cset, dev, reps=5):
@@ -667,7 +714,11 @@ def main():
             "hbm_achieved_GBs": round(hbm_gbs, 1),
             "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
             "copy_kernel_GBs": round(copy_gbs, 1),
+            "hbm_frac_of_copy": round(hbm_gbs / copy_gbs, 4),
+            "kernel_ms_p10_p50_p90": [round(v, 5) for v in r["kern_pct"]],
         },
+        "device": {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                   "cus": props.multi_processor_count, "hip": torch.version.hip},
     }
     if not args.no_cpu:
         log("cpu baseline: oracle on the batch")
@@ -680,6 +731,8 @@ def main():
         sec["diff_affine_8x128"] = run_c4(dev, stream, reps=10)
         log("secondary: 4 x 256^3 nonrigid fwd / fwd+bwd")
         sec["nonrigid_4x256"] = run_c5(dev, stream, reps=5)
+        log("secondary: warp only")
+        sec["warp_only_c3"] = run_warp_only(r["sets"], dev, stream)
         log("secondary: host-to-device FIFO")
         sec["host_fifo_c3"] = run_fifo(r["sets"][0], dev)
         result["secondary"] = sec
