@@ -329,15 +329,19 @@ ctaug_status ctaug_gaussian_smooth(const ctaug_vol *in, ctaug_vol *out, const fl
 /* whole training batch through a job queue; here one launch covers it)      */
 /* ------------------------------------------------------------------------ */
 
-/* One job: exactly the arguments of ctaug_warp_affine.  lbl_in.data == NULL
- * means no labels (then lbl_out is ignored); photo.flags bit 31 set means
- * "no photometrics". */
+/* One job: exactly the arguments of ctaug_warp_affine, or of
+ * ctaug_warp_bspline when ctrl is not NULL (grid = its G).  lbl_in.data ==
+ * NULL means no labels (then lbl_out is ignored); photo.flags bit 31 set means
+ * "no photometrics".  A plan holds either only affine jobs or only B-spline
+ * jobs; B-spline plans always use 8 x 8 x 16 tiles and FP32 LDS cells. */
 typedef struct {
     ctaug_vol img_in, lbl_in, img_out, lbl_out;
     float M[12];
     float fill;
     int32_t label_fill;
     ctaug_photo photo;
+    const float *ctrl;     /* device [3][Gx][Gy][Gz], or NULL */
+    int64_t grid[3];
 } ctaug_job;
 
 #define CTAUG_PHOTO_NONE 0x80000000u
@@ -376,7 +380,7 @@ ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jo
 
 /* Enqueue: upload the job table (async copy from pinned staging) and run one
  * persistent launch that warps every job.  Results equal ctaug_warp_affine
- * on each job, bit for bit. */
+ * (ctaug_warp_bspline) on each job, bit for bit. */
 ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *plan, void *stream);
 
 /* Enqueue only the persistent launch, reading the job table uploaded by the

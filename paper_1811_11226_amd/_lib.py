@@ -46,7 +46,8 @@ class AffineParams(ctypes.Structure):
 class Job(ctypes.Structure):
     _fields_ = [("img_in", Vol), ("lbl_in", Vol), ("img_out", Vol), ("lbl_out", Vol),
                 ("M", ctypes.c_float * 12), ("fill", ctypes.c_float),
-                ("label_fill", ctypes.c_int32), ("photo", Photo)]
+                ("label_fill", ctypes.c_int32), ("photo", Photo), ("ctrl", ctypes.c_void_p),
+                ("grid", ctypes.c_int64 * 3)]
 
 
 class Tuning(ctypes.Structure):

@@ -723,6 +723,7 @@ struct ctaug_batch_plan {
     bool all_i16 = true;                // every job has an int16 input
     bool all_f32 = true;                // every job has an FP32 input
     bool aligned = true;                // every job's output z extent is a multiple of 4
+    bool spline = false;                // B-spline jobs (displacement tiles)
     int num_cu = 256;
     hipEvent_t upload_done = nullptr;
     bool upload_recorded = false;
@@ -758,9 +759,16 @@ ctaug_status job_from_public(const ctaug_job &j, const Tiling &TL, FwdJob &J)
 {
     const bool has_lbl = j.lbl_in.data != nullptr;
     const bool has_photo = !(j.photo.flags & CTAUG_PHOTO_NONE);
-    return make_job(&j.img_in, has_lbl ? &j.lbl_in : nullptr, j.M, nullptr, false, j.fill,
-                    j.label_fill, has_photo ? &j.photo : nullptr, &j.img_out,
-                    has_lbl ? &j.lbl_out : nullptr, TL, J);
+    ctaug_status st = make_job(&j.img_in, has_lbl ? &j.lbl_in : nullptr, j.M, nullptr, false,
+                               j.fill, j.label_fill, has_photo ? &j.photo : nullptr, &j.img_out,
+                               has_lbl ? &j.lbl_out : nullptr, TL, J);
+    if (st != CTAUG_OK || !j.ctrl)
+        return st;
+    if (!grid_valid(j.grid))
+        return CTAUG_ESHAPE;
+    J.ctrl = j.ctrl;
+    J.bs = bspline_geom(j.grid, j.img_out.dim);
+    return CTAUG_OK;
 }
 
 void destroy_graph(ctaug_batch_plan *p)
@@ -779,9 +787,11 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     ctaug_status st = tiling_of(&t, TL);
     if (st != CTAUG_OK)
         return st;
+    if (p->spline)                      // B-spline jobs: displacement tiles, FP32 cells
+        TL = kDispTiling;
     std::vector<int32_t> prefix(p->n + 1, 0);
     int64_t total = 0;
-    p->elem_bytes = (t.lds_format == 1 && p->all_i16) ? 2 : 4;
+    p->elem_bytes = (t.lds_format == 1 && p->all_i16 && !p->spline) ? 2 : 4;
     for (int i = 0; i < p->n; ++i) {
         set_tiles(p->jobs[i], TL);
         if (p->elem_bytes == 2)
@@ -795,7 +805,9 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
         return CTAUG_ESHAPE;
     prefix[p->n] = (int32_t)total;
     int32_t cells = t.lds_cells < 0 ? 0 : t.lds_cells;
-    if (t.lds_cells == 0) {
+    if (p->spline) {
+        cells = lds_cells_for(kDispLdsCells, 4);
+    } else if (t.lds_cells == 0) {
         // the largest footprint of the current jobs, with headroom for later
         // updates; tiles that still exceed it take the direct-gather path
         int64_t need = 0;
@@ -816,7 +828,13 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
     p->TL = TL;
     p->tune = t;
-    p->tune.lds_cells = t.lds_cells < 0 ? -1 : cells;
+    p->tune.lds_cells = t.lds_cells < 0 && !p->spline ? -1 : cells;
+    if (p->spline) {
+        p->tune.tile[0] = 1 << TL.lx;
+        p->tune.tile[1] = 1 << TL.ly;
+        p->tune.tile[2] = 1 << TL.lz;
+        p->tune.lds_format = 0;
+    }
     p->lds_cells = cells;
     p->total = (int32_t)total;
     const int64_t tiles8 = ((total + 7) / 8) * 8;
@@ -829,6 +847,8 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
 
 int batch_mode(const ctaug_batch_plan *p)
 {
+    if (p->spline)
+        return p->all_i16 ? kBatchSplineI16 : p->all_f32 ? kBatchSplineF32 : kBatchSplineMixed;
     if (p->all_i16)
         return p->elem_bytes == 2 ? kBatchI16I16 : kBatchI16F32;
     return p->all_f32 ? kBatchF32 : kBatchMixed;
@@ -872,10 +892,16 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
     ctaug_status st = tiling_of(tune, TL);
     if (st != CTAUG_OK)
         return st;
+    for (int i = 1; i < n_jobs; ++i)
+        if ((jobs[i].ctrl != nullptr) != (jobs[0].ctrl != nullptr))
+            return CTAUG_EINVAL;           // affine and B-spline jobs in one plan
+    if (jobs[0].ctrl)
+        TL = kDispTiling;
     ctaug_batch_plan *p = new (std::nothrow) ctaug_batch_plan();
     if (!p)
         return CTAUG_EINVAL;
     p->n = n_jobs;
+    p->spline = jobs[0].ctrl != nullptr;
     p->jobs.resize(n_jobs);
     p->out_dims.resize(3 * (size_t)n_jobs);
     for (int i = 0; i < n_jobs; ++i) {
@@ -925,6 +951,8 @@ extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug
         return CTAUG_EINVAL;
     std::vector<FwdJob> next(p->n);
     for (int i = 0; i < p->n; ++i) {
+        if ((jobs[i].ctrl != nullptr) != p->spline)
+            return CTAUG_EINVAL;           // the plan holds only affine or only B-spline jobs
         ctaug_status st = job_from_public(jobs[i], p->TL, next[i]);
         if (st != CTAUG_OK)
             return st;

@@ -9,8 +9,15 @@
 namespace ctaug {
 
 hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s);
-// Input / LDS cell types shared by every job of a batch launch.
-enum : int { kBatchMixed = 0, kBatchI16F32 = 1, kBatchI16I16 = 2, kBatchF32 = 3 };
+// Input / LDS cell types shared by every job of a batch launch; the Spline
+// modes warp B-spline jobs (displacement tiles, FP32 LDS cells).
+enum : int { kBatchMixed = 0, kBatchI16F32 = 1, kBatchI16I16 = 2, kBatchF32 = 3,
+             kBatchSplineI16 = 4, kBatchSplineF32 = 5, kBatchSplineMixed = 6 };
+// Displacement warps: 8 x 8 x 16 tiles (one run of 4 z voxels per thread, so
+// that a tile can reduce its coordinate range before staging) and a fixed
+// reservation, since the footprint has no a-priori bound.
+constexpr Tiling kDispTiling = {3, 3, 4};
+constexpr int32_t kDispLdsCells = 10224;
 hipError_t launch_warp_batch(const FwdJob *jobs_dev, const int32_t *prefix_dev, int32_t njobs,
                              int32_t total_tiles, int32_t grid, const Tiling &TL,
                              int32_t lds_cells, int32_t elem_bytes, int mode, bool aligned,

@@ -341,16 +341,27 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
             ++j;
         const FwdJob J = jobs[j];
         const int lt = t - prefix[j];
-        if (MODE == kBatchI16F32)
+        if constexpr (MODE == kBatchSplineI16) {
+            fwd_tile_lt<int16_t, float, ALIGNED, kDispSpline>(J, lt, TL, lds_cells, s_footprint);
+        } else if constexpr (MODE == kBatchSplineF32) {
+            fwd_tile_lt<float, float, ALIGNED, kDispSpline>(J, lt, TL, lds_cells, s_footprint);
+        } else if constexpr (MODE == kBatchSplineMixed) {
+            if (J.dtype == kI16)
+                fwd_tile_lt<int16_t, float, ALIGNED, kDispSpline>(J, lt, TL, lds_cells, s_footprint);
+            else
+                fwd_tile_lt<float, float, ALIGNED, kDispSpline>(J, lt, TL, lds_cells, s_footprint);
+        } else if constexpr (MODE == kBatchI16F32) {
             fwd_tile_lt<int16_t, float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
-        else if (MODE == kBatchI16I16)
+        } else if constexpr (MODE == kBatchI16I16) {
             fwd_tile_lt<int16_t, int16_t, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
-        else if (MODE == kBatchF32)
+        } else if constexpr (MODE == kBatchF32) {
             fwd_tile_lt<float, float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
-        else if (J.dtype == kI16)
-            fwd_tile<int16_t, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
-        else
-            fwd_tile<float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
+        } else {
+            if (J.dtype == kI16)
+                fwd_tile<int16_t, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
+            else
+                fwd_tile<float, ALIGNED, kDispNone>(J, lt, TL, lds_cells, s_footprint);
+        }
     }
 }
 
@@ -443,11 +454,6 @@ static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32
     }
 }
 
-// Displacement warps: 8 x 8 x 16 tiles (one run of 4 z voxels per thread, so
-// that a tile can reduce its coordinate range before staging) and a fixed
-// reservation, since the footprint has no a-priori bound.
-constexpr Tiling kDispTiling = {3, 3, 4};
-constexpr int32_t kDispLdsCells = 10224;
 static_assert(1 << (3 + 3 + 4 - 2) == kThreads, "one run of a displacement tile per thread");
 static_assert(3 * kDispLdsCells >= kSplineTileLdsFloats * (int32_t)sizeof(float),
               "the B-spline scratch of a tile fits its smallest footprint reservation");
@@ -500,6 +506,18 @@ static void launch_batch_mode(int mode, const FwdJob *jobs_dev, const int32_t *p
     case kBatchF32:
         hipLaunchKernelGGL((k_warp_batch<ALIGNED, kBatchF32>), dim3(grid), dim3(kThreads), lds, s,
                            jobs_dev, prefix_dev, njobs, TL, lds_cells);
+        break;
+    case kBatchSplineI16:
+        hipLaunchKernelGGL((k_warp_batch<ALIGNED, kBatchSplineI16>), dim3(grid), dim3(kThreads),
+                           lds, s, jobs_dev, prefix_dev, njobs, TL, lds_cells);
+        break;
+    case kBatchSplineF32:
+        hipLaunchKernelGGL((k_warp_batch<ALIGNED, kBatchSplineF32>), dim3(grid), dim3(kThreads),
+                           lds, s, jobs_dev, prefix_dev, njobs, TL, lds_cells);
+        break;
+    case kBatchSplineMixed:
+        hipLaunchKernelGGL((k_warp_batch<ALIGNED, kBatchSplineMixed>), dim3(grid), dim3(kThreads),
+                           lds, s, jobs_dev, prefix_dev, njobs, TL, lds_cells);
         break;
     default:
         hipLaunchKernelGGL((k_warp_batch<ALIGNED, kBatchMixed>), dim3(grid), dim3(kThreads), lds,

@@ -302,8 +302,15 @@ def copy(src, dst):
 # Batch plan
 # ---------------------------------------------------------------------------
 
-def make_job(img, M, out, lbl=None, lbl_out=None, fill=-1000.0, label_fill=0, photo=None):
+def make_job(img, M, out, lbl=None, lbl_out=None, fill=-1000.0, label_fill=0, photo=None,
+             ctrl=None):
+    """One batch job; with ctrl ([3][Gx][Gy][Gz] float32 on the device) the job
+    is the B-spline warp of warp_bspline."""
     j = _lib.Job()
+    if ctrl is not None:
+        _require(ctrl, "ctrl", (torch.float32,), ndim=4)
+        j.ctrl = ctrl.data_ptr()
+        j.grid = (ctypes.c_int64 * 3)(*ctrl.shape[1:])
     j.img_in = vol(img)
     j.img_out = vol(out)
     if lbl is not None:

@@ -380,6 +380,15 @@ def test_plan_rejects_bad_jobs(L):
     bad.M[0] = math.nan
     jobs = (_lib.Job * 1)(bad)
     assert L.ctaug_batch_plan_create(jobs, 1, None, ctypes.byref(plan)) == EINVAL
+    # B-spline jobs: not mixed with affine ones, and a valid grid
+    sp = _job()
+    sp.ctrl = FAKE
+    sp.grid = (ctypes.c_int64 * 3)(8, 8, 8)
+    jobs = (_lib.Job * 2)(sp, _job())
+    assert L.ctaug_batch_plan_create(jobs, 2, None, ctypes.byref(plan)) == EINVAL
+    sp.grid = (ctypes.c_int64 * 3)(8, 3, 8)
+    jobs = (_lib.Job * 1)(sp)
+    assert L.ctaug_batch_plan_create(jobs, 1, None, ctypes.byref(plan)) == ESHAPE
     assert not plan.value
 
 

@@ -802,6 +802,54 @@ def test_batch_plan_matches_single_calls_and_oracle():
     plan.close()
 
 
+def test_batch_plan_bspline_jobs_match_single_calls():
+    """B-spline jobs in the batched persistent launch (displacement tiles)
+    give the bits of warp_bspline on each volume, across an update and graph
+    replays; the plan reports the displacement tile shape."""
+    rng = np.random.default_rng(101)
+    shapes = [(40, 36, 28), (33, 30, 17), (48, 20, 44), (25, 25, 25)]
+    out_dim = (36, 28, 20)
+    grids = [(8, 8, 8), (6, 7, 5), (5, 6, 9), (4, 4, 4)]
+    items = []
+    for i, (shp, grid) in enumerate(zip(shapes, grids)):
+        img, lbl = phantom_pair(shp, seed=400 + i)
+        prm = draw_affine_params(rng, AugmentRanges(), shp, out_dim)
+        _, M = ctaug.affine_matrix(prm, shp, out_dim)
+        C = (3.0 * rng.standard_normal((3,) + grid)).astype(np.float32)
+        ph = draw_photo(rng, AugmentRanges(), seed=11, volume_id=i)
+        items.append([_t(img), _t(lbl), M, _t(C), ph,
+                      torch.empty(out_dim, dtype=torch.float32, device=DEV),
+                      torch.empty(out_dim, dtype=torch.int8, device=DEV)])
+
+    def jobs():
+        return [ctaug.make_job(im, M, o, lb, lo, photo=ph, ctrl=C)
+                for im, lb, M, C, ph, o, lo in items]
+
+    def check():
+        for im, lb, M, C, ph, o, lo in items:
+            ref, lref = ctaug.warp_bspline(im, M, C, lbl=lb, photo=ph, out_dim=out_dim)
+            assert np.array_equal(_np(o).view(np.uint32), _np(ref).view(np.uint32))
+            assert np.array_equal(_np(lo), _np(lref))
+
+    plan = ctaug.BatchPlan(jobs(), tile=(16, 16, 16))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.launch()
+    torch.cuda.synchronize()
+    check()
+    assert tuple(plan.tuning()[0]) == (8, 8, 16)
+    for it in items:                       # new control grids, then graph replays
+        it[3] = _t((2.0 * rng.standard_normal(tuple(it[3].shape))).astype(np.float32))
+    with torch.cuda.stream(stream):
+        plan.capture()
+        plan.update(jobs())
+        plan.replay()
+        plan.replay()
+    torch.cuda.synchronize()
+    check()
+    plan.close()
+
+
 @pytest.mark.parametrize("tile,wg,lds,fmt", [((4, 8, 32), 0, 0, 0), ((8, 8, 16), 2, 0, 1),
                                              ((2, 4, 64), 1, 2048, 0), ((16, 16, 16), 4, 0, 1),
                                              ((8, 16, 16), 0, -1, 0), ((8, 8, 8), 0, 300, 1),
