@@ -415,7 +415,9 @@ ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *plan);
 
 typedef struct ctaug_pipeline ctaug_pipeline;
 
-/* Create a FIFO of `depth` >= 2 slots of `slot_bytes` bytes each: pinned host
+/* Not thread-safe: one producer thread drives a pipeline.
+ *
+ * Create a FIFO of `depth` >= 2 slots of `slot_bytes` bytes each: pinned host
  * buffers the caller fills, device buffers the warps read, a copy stream and
  * a compute stream (default priority), and per-slot events.  Owned by the
  * pipeline, freed by ctaug_pipeline_destroy.  Errors: EINVAL (depth < 2 or >
