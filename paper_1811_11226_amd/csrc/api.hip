@@ -995,9 +995,14 @@ extern "C" ctaug_status ctaug_batch_plan_run(ctaug_batch_plan *p, void *stream)
 {
     if (!p || !p->upload_recorded)
         return CTAUG_EINVAL;
-    return hip_status(launch_warp_batch(p->table, p->prefix_dev, p->n, p->total, p->grid, p->TL,
-                                        p->lds_cells, p->elem_bytes, batch_mode(p), p->aligned,
-                                        as_stream(stream)));
+    hipStream_t s = as_stream(stream);
+    ctaug_status st = hip_status(launch_warp_batch(p->table, p->prefix_dev, p->n, p->total,
+                                                   p->grid, p->TL, p->lds_cells, p->elem_bytes,
+                                                   batch_mode(p), p->aligned, s));
+    if (st != CTAUG_OK)
+        return st;
+    // a later update must also wait for this launch's reads of the table
+    return hip_status(hipEventRecord(p->upload_done, s));
 }
 
 extern "C" ctaug_status ctaug_copy(const void *src, void *dst, size_t bytes, void *stream)
