@@ -65,6 +65,9 @@ def _declare(L):
     L.orc_warp.argtypes = [_p, _p, _p, _p, _p, _int, _p, _dbl, _int, _p, _int, _u64, _u32, _p,
                            _p, _p, _p]
     L.orc_warp.restype = _int
+    L.orc_warp_points.argtypes = [_p, _p, _p, _p, _p, _int, _p, _dbl, _int, _p, _int, _u64, _u32,
+                                  _p, _p, _p, _i64, _p, _p]
+    L.orc_warp_points.restype = _int
     L.orc_warp_backward.argtypes = [_p, _p, _p, _p, _int, _p, _dbl, _p, _p, _p, _p, _p]
     L.orc_warp_backward.restype = _int
     L.orc_bspline_upsample.argtypes = [_p, _p, _p, _p]
@@ -188,6 +191,35 @@ def warp(img, M, out_dim, lbl=None, disp=None, fill=-1000.0, label_fill=0, photo
     _check(lib().orc_warp(_ptr(img64), _ptr(in_dim), _ptr(lbl8), _ptr(Mf), _ptr(Md), int(exact),
                           _ptr(d), float(fill), int(label_fill), _ptr(ph), window, seed, vol,
                           _ptr(occ), _ptr(od), _ptr(out), _ptr(lout)))
+    return out, lout
+
+
+def warp_points(img, M, out_dim, idx, lbl=None, disp=None, fill=-1000.0, label_fill=0,
+                photo=None, exact=False, want_img=True, want_lbl=None):
+    """The forward warp at the output voxels with linear indices idx only
+    (same arithmetic as warp).  Returns (values float64 [len(idx)] or None,
+    labels int8 [len(idx)] or None)."""
+    img64 = _c(img, np.float64)
+    in_dim = _dims(img64.shape)
+    od = _dims(out_dim)
+    if want_lbl is None:
+        want_lbl = lbl is not None
+    ix = _c(idx, np.int64).ravel()
+    lbl8 = _c(lbl, np.int8)
+    Mf = np.asarray(M, dtype=np.float32)
+    Md = np.asarray(M, dtype=np.float64)
+    d = _c(disp, np.float32)
+    out = np.empty(ix.size, dtype=np.float64) if want_img else None
+    lout = np.empty(ix.size, dtype=np.int8) if want_lbl else None
+    ph = _photo6(photo) if photo is not None else None
+    seed = int(photo.seed) if photo is not None else 0
+    vol = int(photo.volume_id) if photo is not None else 0
+    window = int(bool(photo.window)) if photo is not None else 0
+    occ = _occ(photo)
+    _check(lib().orc_warp_points(_ptr(img64), _ptr(in_dim), _ptr(lbl8), _ptr(Mf), _ptr(Md),
+                                 int(exact), _ptr(d), float(fill), int(label_fill), _ptr(ph),
+                                 window, seed, vol, _ptr(occ), _ptr(od), _ptr(ix), ix.size,
+                                 _ptr(out), _ptr(lout)))
     return out, lout
 
 

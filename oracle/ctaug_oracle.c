@@ -381,6 +381,48 @@ static int dims_ok(const int64_t *d)
     return d && d[0] >= 0 && d[1] >= 0 && d[2] >= 0;
 }
 
+typedef struct {
+    const double *img;
+    const int64_t *in_dim;
+    const int8_t *lbl;
+    double fill;
+    int label_fill;
+    const double *photo;
+    int window;
+    uint64_t seed;
+    uint32_t vol;
+    const double *occ;
+} warp_ctx;
+
+/* One output voxel (x, y, z) with linear index v of the forward warp. */
+static void warp_voxel(const coord_ctx *cc, const warp_ctx *w, int64_t x, int64_t y, int64_t z,
+                       int64_t v, double *out, int8_t *lbl_out)
+{
+    double q[3];
+    float qf[3];
+    coord(cc, x, y, z, v, q, qf);
+    if (out) {
+        /* I_occ: the occluded slab is 0, elsewhere the warped image */
+        double V = occluded(w->occ, z) ? 0.0 : trilinear(w->img, w->in_dim, q, w->fill, NULL);
+        *out = w->photo ? photometric(V, w->photo, w->window, w->seed, w->vol, (uint64_t)v) : V;
+    }
+    if (lbl_out)
+        *lbl_out = (int8_t)nn_label(w->lbl, w->in_dim, qf, w->label_fill);
+}
+
+static int warp_args_ok(const double *img, const int64_t *in_dim, const int8_t *lbl,
+                        const float *Mf, const double *Md, int exact, const int64_t *out_dim,
+                        const double *out, const int8_t *lbl_out)
+{
+    if (!dims_ok(in_dim) || !dims_ok(out_dim))
+        return 0;
+    if ((exact && !Md) || (!exact && !Mf))
+        return 0;
+    if ((out && !img) || (lbl_out && !lbl))
+        return 0;
+    return 1;
+}
+
 /* Forward warp: out(p) = photometric(I_in(q(p))), lbl_out(p) = L_in(nn(q(p))).
  * img/out may be NULL independently of lbl/lbl_out.  photo == NULL leaves
  * the interpolated value unchanged (identity photometrics). */
@@ -390,30 +432,46 @@ int orc_warp(const double *img, const int64_t *in_dim, const int8_t *lbl,
              const double *photo, int window, uint64_t seed, uint32_t vol, const double *occ,
              const int64_t *out_dim, double *out, int8_t *lbl_out)
 {
-    if (!dims_ok(in_dim) || !dims_ok(out_dim))
-        return ORC_EINVAL;
-    if ((exact && !Md) || (!exact && !Mf))
-        return ORC_EINVAL;
-    if ((out && !img) || (lbl_out && !lbl))
+    if (!warp_args_ok(img, in_dim, lbl, Mf, Md, exact, out_dim, out, lbl_out))
         return ORC_EINVAL;
     const int64_t X = out_dim[0], Y = out_dim[1], Z = out_dim[2];
     coord_ctx cc = { Mf, Md, exact, disp, X * Y * Z };
+    warp_ctx w = { img, in_dim, lbl, fill, label_fill, photo, window, seed, vol, occ };
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < X; ++x)
         for (int64_t y = 0; y < Y; ++y)
             for (int64_t z = 0; z < Z; ++z) {
                 int64_t v = (x * Y + y) * Z + z;
-                double q[3];
-                float qf[3];
-                coord(&cc, x, y, z, v, q, qf);
-                if (out) {
-                    /* I_occ: the occluded slab is 0, elsewhere the warped image */
-                    double V = occluded(occ, z) ? 0.0 : trilinear(img, in_dim, q, fill, NULL);
-                    out[v] = photo ? photometric(V, photo, window, seed, vol, (uint64_t)v) : V;
-                }
-                if (lbl_out)
-                    lbl_out[v] = (int8_t)nn_label(lbl, in_dim, qf, label_fill);
+                warp_voxel(&cc, &w, x, y, z, v, out ? out + v : NULL, lbl_out ? lbl_out + v : NULL);
             }
+    return ORC_OK;
+}
+
+/* The same warp evaluated only at the npts output voxels with linear indices
+ * idx[k] (each in [0, X*Y*Z)); out[k] / lbl_out[k] receive voxel idx[k].  A
+ * displacement field, when given, is still the whole [3][X][Y][Z] field. */
+int orc_warp_points(const double *img, const int64_t *in_dim, const int8_t *lbl,
+                    const float *Mf, const double *Md, int exact, const float *disp,
+                    double fill, int label_fill,
+                    const double *photo, int window, uint64_t seed, uint32_t vol,
+                    const double *occ, const int64_t *out_dim, const int64_t *idx, int64_t npts,
+                    double *out, int8_t *lbl_out)
+{
+    if (!warp_args_ok(img, in_dim, lbl, Mf, Md, exact, out_dim, out, lbl_out) || npts < 0 ||
+        (npts > 0 && !idx))
+        return ORC_EINVAL;
+    const int64_t X = out_dim[0], Y = out_dim[1], Z = out_dim[2];
+    for (int64_t k = 0; k < npts; ++k)
+        if (idx[k] < 0 || idx[k] >= X * Y * Z)
+            return ORC_EINVAL;
+    coord_ctx cc = { Mf, Md, exact, disp, X * Y * Z };
+    warp_ctx w = { img, in_dim, lbl, fill, label_fill, photo, window, seed, vol, occ };
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < npts; ++k) {
+        const int64_t v = idx[k];
+        const int64_t z = v % Z, y = (v / Z) % Y, x = v / (Y * Z);
+        warp_voxel(&cc, &w, x, y, z, v, out ? out + k : NULL, lbl_out ? lbl_out + k : NULL);
+    }
     return ORC_OK;
 }
 

@@ -407,6 +407,29 @@ def test_constant_displacement_equals_shift():
     assert np.array_equal(a, b) and np.array_equal(la, lb)
 
 
+def test_point_sampled_warp_equals_whole_volume_warp():
+    """The point-sampled entry (used at sizes where the whole volume is too slow
+    for the oracle) indexes output voxels as the whole-volume warp does."""
+    rng = np.random.default_rng(16)
+    in_dim, out_dim = (14, 12, 10), (9, 13, 11)
+    img, lbl = phantom_pair(in_dim, seed=34)
+    M = _dyadic_M(rng, in_dim, out_dim)
+    disp = rng.normal(0.0, 1.5, size=(3,) + out_dim).astype(np.float32)
+    ph = PhotoParams(gain=1.05, offset=7.0, sigma=10.0, window=True, gamma=0.9, seed=11,
+                     volume_id=3)
+    n = int(np.prod(out_dim))
+    idx = np.concatenate([[0, n - 1], rng.integers(0, n, size=200)])
+    for d in (None, disp):
+        full, lfull = oracle.warp(img, M, out_dim, lbl=lbl, disp=d, photo=ph)
+        pts, lpts = oracle.warp_points(img, M, out_dim, idx, lbl=lbl, disp=d, photo=ph)
+        assert np.array_equal(pts, full.ravel()[idx]) and np.array_equal(lpts, lfull.ravel()[idx])
+    e, le = oracle.warp_points(img, M, out_dim, np.zeros(0, np.int64), lbl=lbl)
+    assert e.size == 0 and le.size == 0
+    for bad in (-1, n):
+        with pytest.raises(ValueError):
+            oracle.warp_points(img, M, out_dim, np.array([bad]))
+
+
 # --------------------------------------------------------------------------
 # C-P15 and the transform sampler: centre formula, rotations vs SciPy
 # --------------------------------------------------------------------------
