@@ -345,7 +345,9 @@ def run_c4(dev, stream, reps):
     outs = [torch.empty(j.out_dim, dtype=torch.float32, device=dev) for j in jobs]
     plan = ctaug.BatchPlan([ctaug.make_job(imgs[k], Ms[k], outs[k], fill=jobs[k].fill)
                             for k in range(len(jobs))])
-    g_imgs = [torch.empty_like(i) for i in imgs]
+    # the image gradients of the batch live in one buffer, cleared by one fill
+    g_all = torch.empty((len(jobs),) + tuple(imgs[0].shape), dtype=torch.float32, device=dev)
+    g_imgs = [g_all[k] for k in range(len(jobs))]
     g_M = torch.empty(12, dtype=torch.float64, device=dev)
     ws_bytes = ctaug.ops.warp_backward_workspace(jobs[0].out_dim)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
@@ -360,8 +362,8 @@ def run_c4(dev, stream, reps):
 
     def bwd():
         st = ctaug.ops._stream()
+        g_all.zero_()
         for k in range(len(jobs)):
-            g_imgs[k].zero_()
             r = L.ctaug_warp_affine_backward(ctypes.byref(vi[k]), Mc[k], jobs[k].fill,
                                              ctypes.byref(vg[k]), ctypes.byref(vgi[k]),
                                              ctypes.c_void_p(g_M.data_ptr()),
@@ -401,7 +403,8 @@ def run_c5(dev, stream, reps):
     G = (ctypes.c_int64 * 3)(*ctrls[0].shape[1:])
     ws_bytes = int(L.ctaug_warp_bspline_backward_workspace(od, G))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    g_imgs = [torch.empty_like(i) for i in imgs]
+    g_all = torch.empty((len(jobs),) + tuple(imgs[0].shape), dtype=torch.float32, device=dev)
+    g_imgs = [g_all[k] for k in range(len(jobs))]
     g_Ms = [torch.empty(12, dtype=torch.float64, device=dev) for _ in jobs]
     g_cs = [torch.empty_like(c) for c in cs]
     vi = [ctaug.ops.vol(i) for i in imgs]
@@ -415,8 +418,8 @@ def run_c5(dev, stream, reps):
 
     def bwd():
         st = ctaug.ops._stream()
+        g_all.zero_()
         for k, j in enumerate(jobs):
-            g_imgs[k].zero_()
             r = L.ctaug_warp_bspline_backward(ctypes.byref(vi[k]), Mc[k], P(cs[k].data_ptr()), G,
                                               j.fill, ctypes.byref(vg[k]), ctypes.byref(vgi[k]),
                                               P(g_Ms[k].data_ptr()), P(g_cs[k].data_ptr()),
