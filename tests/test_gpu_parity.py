@@ -573,6 +573,37 @@ def test_affine_backward_param_only_and_singular_map():
     assert_grad(_np(g_M), r_M, "g_M singular")
 
 
+def test_backward_calls_on_two_streams_agree_with_one_stream():
+    """Independent backward calls running at once on two streams, each with
+    its own workspace, give the parameter gradients bit for bit and the image
+    gradients within the bar of the same calls made one after another."""
+    rng = np.random.default_rng(61)
+    dims = (40, 36, 44)
+    cases = []
+    for k in range(6):
+        img, _ = phantom_pair(dims, seed=400 + k)
+        prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+        _, M = ctaug.affine_matrix(prm, dims, dims)
+        g = rng.standard_normal(dims).astype(np.float32)
+        cases.append((_t(img.astype(np.float32)), M, _t(g)))
+    seq = [ctaug.warp_affine_backward(i, M, g) for i, M, g in cases]
+    torch.cuda.synchronize()
+    side = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ready = torch.cuda.Event()
+    ready.record()
+    for s in side:
+        s.wait_event(ready)
+    par = []
+    for k, (i, M, g) in enumerate(cases):
+        with torch.cuda.stream(side[k % 2]):
+            par.append(ctaug.warp_affine_backward(i, M, g))
+    for s in side:
+        s.synchronize()
+    for k, ((gi, gM), (pi, pM)) in enumerate(zip(seq, par)):
+        assert np.array_equal(_np(gM).view(np.uint64), _np(pM).view(np.uint64)), f"g_M {k}"
+        assert_grad(_np(pi), _np(gi).astype(np.float64), f"g_img {k}")
+
+
 def test_affine_backward_adjoint_identity_gpu():
     rng = np.random.default_rng(10)
     dims = (40, 40, 40)
