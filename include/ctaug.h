@@ -374,8 +374,10 @@ ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n_jobs,
 
 /* Replace the jobs' contents (pointers, matrices, photometrics).  Every job
  * must keep the output dims it had at plan creation (else ESHAPE), and an
- * FP32 input is refused (EDTYPE) in a plan created with only int16 inputs.  Waits (host side) for
- * the previous launch's table upload to finish before overwriting staging. */
+ * FP32 input is refused (EDTYPE) in a plan created with only int16 inputs.
+ * Waits (host side) until the plan's last launch, run or replay has finished
+ * on the GPU (its upload reads the staging buffer, its kernel the table)
+ * before overwriting staging. */
 ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jobs);
 
 /* Enqueue: upload the job table (async copy from pinned staging) and run one
@@ -385,7 +387,8 @@ ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *plan, void *stream);
 
 /* Enqueue only the persistent launch, reading the job table uploaded by the
  * last launch/replay (no upload): re-runs the same descriptors, e.g. after the
- * caller refilled the same input buffers in place. */
+ * caller refilled the same input buffers in place.  EINVAL before the first
+ * launch or replay. */
 ctaug_status ctaug_batch_plan_run(ctaug_batch_plan *plan, void *stream);
 
 /* Capture ctaug_batch_plan_launch on `stream` into a HIP graph owned by the
