@@ -13,10 +13,12 @@ step finds its inputs cache-resident, and each batch cycles through four
 parameter draws.
 
 Also reported in the same JSON line: the kernel-only roofline of the fused
-batched kernel against HBM bandwidth, the CPU oracle timed on this host, and
-secondary workloads (full-resolution 512x512x320 volume; forward and
-forward+backward of the differentiable warp on 8 x 128^3; the nonrigid
-B-spline warp on 4 x 256^3).
+batched kernel (timed over the same input sets and parameter draws as the
+steps) against the VALU issue peak, with its fraction of HBM bandwidth
+beside it; the CPU oracle timed on this host; and secondary workloads
+(full-resolution 512x512x320 volume; forward and forward+backward of the
+differentiable warp on 8 x 128^3; the nonrigid B-spline warp on 4 x 256^3;
+the warp alone; the host-to-device FIFO).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-secondary]
        [--no-cpu] [--profile]
