@@ -631,7 +631,8 @@ __global__ __launch_bounds__(64) void k_reduce_ctrl_rows(const double *__restric
         return;
     const int32_t r0 = blockIdx.y * chunk, r1 = min(r0 + chunk, rows);
     double s = 0.0;
-    for (int32_t r = r0; r < r1; ++r)
+#pragma unroll 8
+    for (int32_t r = r0; r < r1; ++r)          // loads issue ahead; the sum keeps its order
         s += part[(int64_t)r * n + e];
     groups[(int64_t)blockIdx.y * n + e] = s;
 }
@@ -645,7 +646,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce_ctrl_groups(const double *_
     if (e >= n)
         return;
     double s = 0.0;
-    for (int32_t g = 0; g < ngroups; ++g)
+#pragma unroll 8
+    for (int32_t g = 0; g < ngroups; ++g)      // loads issue ahead; the sum keeps its order
         s += groups[(int64_t)g * n + e];
     out[e] = (float)s;
 }
