@@ -599,7 +599,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce12(const double *__restrict_
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
 
-    for (int r = threadIdx.x; r < n; r += kThreads)
+#pragma unroll 4
+    for (int r = threadIdx.x; r < n; r += kThreads)   // loads issue ahead; sums keep their order
 #pragma unroll
         for (int i = 0; i < 12; ++i)
             acc[i] += partials[(int64_t)r * 12 + i];
