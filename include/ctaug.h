@@ -63,14 +63,33 @@ typedef enum {
     CTAUG_I8 = 2           /* int8 labels */
 } ctaug_dtype;
 
-/* A dense volume.  data: device pointer; dim: X, Y, Z (each >= 0).
- * Element counts up to 2^31 - 1 per volume are supported (FP32 input images:
- * up to 2^30 - 1, so that their byte size fits a 32-bit buffer range). */
+/* A volume.  data: device pointer to element (0,0,0); dim: X, Y, Z (each
+ * >= 0); stride: element strides along X, Y, Z.  stride = {0, 0, 0} means
+ * dense C order ({Y*Z, Z, 1}).
+ *
+ * Strided volumes (e.g. a random training crop, Sec. "Pre- and
+ * post-processing", passed as a view of the whole scan) are accepted for the
+ * INPUT image and label of the warps, their batch jobs and the image read by
+ * the adjoints; every other volume argument must be dense (ESHAPE
+ * otherwise).  A strided volume keeps z contiguous: stride[2] == 1,
+ * stride[1] >= dim[2], and stride[0] a multiple of stride[1] with
+ * stride[0] / stride[1] >= dim[1] (the layout of any box cut out of a dense
+ * parent volume).  A label input must have its image's strides.
+ *
+ * Size limits (ESHAPE beyond them):
+ *  - every volume: at most 2^31 - 1 elements, and its extent
+ *    (X-1) stride[0] + (Y-1) stride[1] + Z at most 2^31 - 1 (FP32 input
+ *    images: 2^30 - 1, so that their byte extent fits a 32-bit buffer range);
+ *  - gathered inputs (image and labels of the warps, the adjoints' image):
+ *    their offsets are formed with 24-bit multiplies, so the row count
+ *    (X-1) stride[0]/stride[1] + Y must be at most 2^24 and the row pitch
+ *    stride[1] below 2^24 (dense: X*Y <= 2^24 and Z < 2^24). */
 typedef struct {
     void *data;
     int32_t dtype;         /* ctaug_dtype */
     int32_t reserved;      /* must be 0 */
     int64_t dim[3];
+    int64_t stride[3];     /* elements; {0, 0, 0} = dense */
 } ctaug_vol;
 
 #define CTAUG_PHOTO_WINDOW 1u   /* apply window [win_lo, win_hi] -> [0,1] and gamma */
@@ -386,9 +405,9 @@ ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jo
 ctaug_status ctaug_batch_plan_launch(ctaug_batch_plan *plan, void *stream);
 
 /* Enqueue only the persistent launch, reading the job table uploaded by the
- * last launch/replay (no upload): re-runs the same descriptors, e.g. after the
- * caller refilled the same input buffers in place.  EINVAL before the first
- * launch or replay. */
+ * last launch, replay or autotune (no upload): re-runs the same descriptors,
+ * e.g. after the caller refilled the same input buffers in place.  EINVAL
+ * before the first launch or replay. */
 ctaug_status ctaug_batch_plan_run(ctaug_batch_plan *plan, void *stream);
 
 /* Capture ctaug_batch_plan_launch on `stream` into a HIP graph owned by the

@@ -26,7 +26,8 @@ class CtaugError(RuntimeError):
 
 class Vol(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("dim", ctypes.c_int64 * 3)]
+                ("reserved", ctypes.c_int32), ("dim", ctypes.c_int64 * 3),
+                ("stride", ctypes.c_int64 * 3)]
 
 
 class Photo(ctypes.Structure):

@@ -17,6 +17,7 @@ namespace {
 
 constexpr int64_t kMaxElems = 2147483647LL;   // int32 linear indices in the kernels
 constexpr int64_t kMaxF32In = 1073741823LL;   // FP32 input bytes must fit a 32-bit buffer range
+constexpr int64_t kMax24 = 1LL << 24;          // operands of the kernels' 24-bit multiplies
 constexpr Tiling kDefaultTiling = {3, 4, 4};   // 8 x 16 x 16 output voxels per workgroup
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -36,8 +37,47 @@ bool dims_valid(const int64_t d[3])
     return d[0] * d[1] <= kMaxElems && d[0] * d[1] * d[2] <= kMaxElems;
 }
 
-// Validate a volume argument; `allowed` is a bit set of dtypes.
-ctaug_status check_vol(const ctaug_vol *v, unsigned allowed)
+// Element strides of a volume: {0,0,0} = dense.  A strided layout keeps z
+// contiguous and its x stride a whole number of y rows (any box cut out of a
+// dense parent).  Writes the row pitch sy (elements between y rows) and the
+// rows per x plane ry; false on a malformed layout.
+bool vol_layout(const ctaug_vol *v, int64_t &ry, int64_t &sy)
+{
+    const int64_t *d = v->dim, *st = v->stride;
+    if (st[0] == 0 && st[1] == 0 && st[2] == 0) {
+        ry = d[1];
+        sy = d[2];
+        return true;
+    }
+    if (st[2] != 1 || st[1] < 1 || st[0] < 1 || st[1] > kMaxElems || st[0] > kMaxElems)
+        return false;
+    if (st[1] < d[2] || st[0] % st[1] != 0 || st[0] / st[1] < d[1])
+        return false;
+    ry = st[0] / st[1];
+    sy = st[1];
+    return true;
+}
+
+bool is_dense(const ctaug_vol *v)
+{
+    int64_t ry = 0, sy = 0;
+    if (!vol_layout(v, ry, sy))
+        return false;
+    return nelem(v->dim) == 0 || (ry == v->dim[1] && sy == v->dim[2]);
+}
+
+// Elements from the first to one past the last element of the volume.
+int64_t vol_extent(const ctaug_vol *v)
+{
+    int64_t ry = 0, sy = 0;
+    if (nelem(v->dim) == 0 || !vol_layout(v, ry, sy))
+        return 0;
+    return ((v->dim[0] - 1) * ry + (v->dim[1] - 1)) * sy + v->dim[2];
+}
+
+// Validate a volume argument; `allowed` is a bit set of dtypes; `strided`:
+// the argument may be a strided view (else it must be dense).
+ctaug_status check_vol(const ctaug_vol *v, unsigned allowed, bool strided = false)
 {
     if (!v || v->reserved != 0)
         return CTAUG_EINVAL;
@@ -45,9 +85,35 @@ ctaug_status check_vol(const ctaug_vol *v, unsigned allowed)
         return CTAUG_EDTYPE;
     if (!dims_valid(v->dim))
         return CTAUG_ESHAPE;
+    int64_t ry = 0, sy = 0;
+    if (!vol_layout(v, ry, sy) || (!strided && !is_dense(v)))
+        return CTAUG_ESHAPE;
+    if (nelem(v->dim) > 0) {           // extent within int32 element offsets
+        const int64_t rows = (v->dim[0] - 1) * ry + (v->dim[1] - 1);
+        if (rows > kMaxElems || rows * sy + v->dim[2] > kMaxElems)
+            return CTAUG_ESHAPE;
+    }
     if (!v->data && nelem(v->dim) > 0)
         return CTAUG_EINVAL;
     return CTAUG_OK;
+}
+
+// A gathered input: offsets (ix ry + iy) sy + iz are formed with 24-bit
+// multiplies, whose operands must stay below 2^24.
+bool gather_addressable(const ctaug_vol *v)
+{
+    int64_t ry = 0, sy = 0;
+    if (nelem(v->dim) == 0)
+        return true;
+    if (!vol_layout(v, ry, sy))
+        return false;
+    return (v->dim[0] - 1) * ry + v->dim[1] <= kMax24 && sy < kMax24;
+}
+
+bool same_layout(const ctaug_vol *a, const ctaug_vol *b)
+{
+    int64_t ra = 0, sa = 0, rb = 0, sb = 0;
+    return vol_layout(a, ra, sa) && vol_layout(b, rb, sb) && ra == rb && sa == sb;
 }
 
 bool same_dims(const ctaug_vol *a, const ctaug_vol *b)
@@ -155,16 +221,20 @@ ctaug_status make_job(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const fl
                       const ctaug_vol *lbl_out, const Tiling &TL, FwdJob &J)
 {
     ctaug_status st;
-    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16, true)) != CTAUG_OK)
         return st;
-    if (img_in->dtype == CTAUG_F32 && nelem(img_in->dim) > kMaxF32In)
+    if (img_in->dtype == CTAUG_F32 && vol_extent(img_in) > kMaxF32In)
+        return CTAUG_ESHAPE;
+    if (!gather_addressable(img_in))
         return CTAUG_ESHAPE;
     if ((st = check_vol(img_out, 1u << CTAUG_F32)) != CTAUG_OK)
         return st;
     if (lbl_in) {
-        if ((st = check_vol(lbl_in, 1u << CTAUG_I8)) != CTAUG_OK)
+        if ((st = check_vol(lbl_in, 1u << CTAUG_I8, true)) != CTAUG_OK)
             return st;
         if (!same_dims(lbl_in, img_in))
+            return CTAUG_ESHAPE;
+        if (nelem(img_in->dim) > 0 && !same_layout(lbl_in, img_in))
             return CTAUG_ESHAPE;
         if (!lbl_out)
             return CTAUG_EINVAL;
@@ -196,6 +266,13 @@ ctaug_status make_job(const ctaug_vol *img_in, const ctaug_vol *lbl_in, const fl
     J.nx = (int32_t)img_in->dim[0];
     J.ny = (int32_t)img_in->dim[1];
     J.nz = (int32_t)img_in->dim[2];
+    {
+        int64_t ry = 0, sy = 0;
+        (void)vol_layout(img_in, ry, sy);
+        J.in_ry = (int32_t)ry;
+        J.in_sy = (int32_t)sy;
+        J.in_extent = (int32_t)vol_extent(img_in);
+    }
     J.ox = (int32_t)img_out->dim[0];
     J.oy = (int32_t)img_out->dim[1];
     J.oz = (int32_t)img_out->dim[2];
@@ -441,7 +518,7 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
                                   size_t ws_bytes, void *stream)
 {
     ctaug_status st;
-    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16, true)) != CTAUG_OK)
         return st;
     if ((st = check_vol(grad_out, 1u << CTAUG_F32)) != CTAUG_OK)
         return st;
@@ -523,7 +600,7 @@ extern "C" ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, con
                                                     void *stream)
 {
     ctaug_status st;
-    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16)) != CTAUG_OK)
+    if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16, true)) != CTAUG_OK)
         return st;
     if ((st = check_vol(grad_out, 1u << CTAUG_F32)) != CTAUG_OK)
         return st;
@@ -780,7 +857,11 @@ void destroy_graph(ctaug_batch_plan *p)
 }
 
 // Recompute tile counts / prefix sums / grid for the plan's tiling and upload
-// the prefix table (synchronous: only at creation and retuning).
+// the prefix and job tables (synchronous: only at creation and retuning).
+// Both uploads wait for the plan's last launch, run or replay first, so that
+// no kernel still running reads a prefix table of one tiling beside a job
+// table of another; afterwards the device tables agree with the new tiling,
+// so a later run() (no upload) decodes tiles consistently.
 ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
 {
     Tiling TL;
@@ -820,12 +901,14 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     }
     for (int i = 0; i < p->n; ++i)
         set_subtiles(p->jobs[i], TL, cells);
-    if (hipMemcpy(p->prefix_dev, prefix.data(), sizeof(int32_t) * (p->n + 1),
-                  hipMemcpyHostToDevice) != hipSuccess)
-        return CTAUG_EHIP;
     if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
         return CTAUG_EHIP;
     std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
+    if (hipMemcpy(p->prefix_dev, prefix.data(), sizeof(int32_t) * (p->n + 1),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->table, p->staging, sizeof(FwdJob) * p->n, hipMemcpyHostToDevice) !=
+            hipSuccess)
+        return CTAUG_EHIP;
     p->TL = TL;
     p->tune = t;
     p->tune.lds_cells = t.lds_cells < 0 && !p->spline ? -1 : cells;
@@ -1243,6 +1326,8 @@ extern "C" ctaug_status ctaug_pipeline_submit(ctaug_pipeline *p, const ctaug_vol
 {
     if (!p || p->held < 0 || !img_host)
         return CTAUG_EINVAL;
+    if (!is_dense(img_host) || (lbl_host && !is_dense(lbl_host)))
+        return CTAUG_ESHAPE;           // slot volumes are copied as dense byte ranges
     const int32_t s = p->held;
     size_t io = 0, ib = 0, lo = 0, lb = 0;
     if (!slot_offset(img_host, p->host[s], p->slot_bytes, io, ib))

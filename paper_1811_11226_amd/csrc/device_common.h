@@ -50,6 +50,8 @@ struct FwdJob {
     BsplineGeom bs;                    // geometry of ctrl over the output
     int32_t dtype;
     int32_t nx, ny, nz;
+    int32_t in_ry, in_sy;              // input layout: rows per x plane, elements per y row
+    int32_t in_extent;                 // elements from the first to past the last input voxel
     int32_t ox, oy, oz;
     uint32_t flags;
     float M[12];                       // [A|b] row-major
@@ -166,34 +168,39 @@ __device__ __forceinline__ float tri(const float k[8], float tx, float ty, float
     return lerp(lerp(e00, e01, ty), lerp(e10, e11, ty), tx);
 }
 
-// Input volume geometry for gathers: dims, byte strides between x / y
-// neighbours, and the buffer resources of image and labels.
+// Input volume geometry for gathers: dims, layout (ry rows per x plane, sy
+// elements per y row, z contiguous), byte strides between x / y neighbours,
+// and the buffer resources of image and labels (which share the layout).
 struct Src {
     rsrc_t img, lbl;
     int32_t nx, ny, nz;
+    int32_t ry, rsy;                   // rows per x plane, elements per y row
     int32_t sy, sx, sxy;               // byte offsets of the +y, +x, +x+y corner rows
 };
 
-template <typename T>
-__device__ __forceinline__ Src make_src(const void *img, const int8_t *lbl, int32_t nx, int32_t ny,
-                                        int32_t nz)
+template <typename T> __device__ __forceinline__ Src make_src(const FwdJob &J)
 {
     Src S;
-    const uint32_t n = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
-    S.img = make_rsrc(img, n * (uint32_t)sizeof(T));
-    S.lbl = make_rsrc(lbl, lbl ? n : 0u);
-    S.nx = nx;
-    S.ny = ny;
-    S.nz = nz;
-    S.sy = nz * (int32_t)sizeof(T);
-    S.sx = ny * nz * (int32_t)sizeof(T);
+    const uint32_t n = (uint32_t)J.in_extent;
+    S.img = make_rsrc(J.img, n * (uint32_t)sizeof(T));
+    S.lbl = make_rsrc(J.lbl, J.lbl ? n : 0u);
+    S.nx = J.nx;
+    S.ny = J.ny;
+    S.nz = J.nz;
+    S.ry = J.in_ry;
+    S.rsy = J.in_sy;
+    S.sy = J.in_sy * (int32_t)sizeof(T);
+    S.sx = J.in_ry * J.in_sy * (int32_t)sizeof(T);
     S.sxy = S.sx + S.sy;
     return S;
 }
 
+// Element offset of input voxel (ix, iy, iz) inside the volume: (ix ry + iy)
+// sy + iz with 24-bit multiplies (the host admits only layouts whose row
+// count and row pitch stay below 2^24).
 __device__ __forceinline__ uint32_t elem_index(const Src &S, int32_t ix, int32_t iy, int32_t iz)
 {
-    return mul24(mul24((uint32_t)ix, (uint32_t)S.ny) + (uint32_t)iy, (uint32_t)S.nz) + (uint32_t)iz;
+    return mul24(mul24((uint32_t)ix, (uint32_t)S.ry) + (uint32_t)iy, (uint32_t)S.rsy) + (uint32_t)iz;
 }
 
 // Sample whose cell [i0, i0+1]^3 is known to lie inside the volume: one VGPR

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     const int per = (ntiles + 7) >> 3;
     const int start = (b & 7) * per;
     const int end = min(start + per, ntiles);
-    const Src src = make_src<T>(J.img, nullptr, J.nx, J.ny, J.nz);
+    const Src src = make_src<T>(J);
     gconst<float> *disp = gc<float>(J.disp);
     const int32_t nvox = J.ox * J.oy * J.oz;
     const bool empty_in = J.nx == 0 || J.ny == 0 || J.nz == 0;   // every sample is fill
@@ -437,13 +437,16 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                                     for (int c = 0; c < 2; ++c) {
                                         const int32_t cx = i0[0] + a, cy = i0[1] + bb,
                                                       cz = i0[2] + c;
-                                        const float w = wx[a] * wy[bb] * wz[c];
+                                        // zero contributions are skipped; a non-finite
+                                        // g reaches every in-volume corner (0 * inf and
+                                        // 0 * NaN are NaN), as in the per-corner path
+                                        const float cw = wx[a] * wy[bb] * wz[c] * gp;
                                         const bool ok = cx >= 0 && cx < J.nx && cy >= 0 &&
                                                         cy < J.ny && cz >= 0 && cz < J.nz &&
-                                                        w != 0.0f;
+                                                        cw != 0.0f;
                                         if (ok)
                                             unsafeAtomicAdd(g_img + (cx * J.ny + cy) * J.nz + cz,
-                                                            w * gp);
+                                                            cw);
                                     }
                         }
                     }
@@ -476,11 +479,16 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                               s_ctrl);
         if (lds) {
             if (g_img) {
+                // the tile's largest |g|; +inf when any g is not finite (NaN
+                // included, which fmaxf alone would drop), which sends the tile
+                // to the per-corner FP32 path below
                 float gm = 0.0f;
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (live[k])
-                        gm = fmaxf(gm, fabsf(gk[k]));
+                    if (live[k]) {
+                        const float a = fabsf(gk[k]);
+                        gm = a <= 3.40282347e38f ? fmaxf(gm, a) : __builtin_inff();
+                    }
                 gm = block_max(gm, s_gmax);
                 // x-planes of 64-bit accumulators that fit the footprint reservation
                 const int planes = (lds_cells >> 1) / sxy;
@@ -540,7 +548,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                         __syncthreads();   // LDS is reused next
                     }
                 } else if (gm != 0.0f) {
-                    // non-finite gradients: FP32 global atomics per corner
+                    // non-finite gradients (or a footprint too large for one
+                    // x-plane of accumulators): FP32 global atomics per corner
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         if (!live[k])

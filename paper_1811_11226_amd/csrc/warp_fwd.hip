@@ -44,7 +44,7 @@ template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL, int DISP>
 __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &SL,
                                          const LT *s_img, const int8_t *s_lbl, const RunQ &Q)
 {
-    const Src S = make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz);
+    const Src S = make_src<T>(J);
     gmut<float> *out = gm<float>(J.out);
     gmut<int8_t> *lout = gm<int8_t>(J.lout);
     Photo P = photo_of(J);
@@ -186,7 +186,7 @@ __device__ __forceinline__ void fwd_box_l(const FwdJob &J, const TileGeom &G, co
     if (G.cls == kOutside) {
         run_tile<T, LT, kPathOutside, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
     } else if (G.lds) {
-        stage_footprint<T, LT>(J, make_src<T>(J.img, J.lbl, J.nx, J.ny, J.nz), G, s_img, s_lbl);
+        stage_footprint<T, LT>(J, make_src<T>(J), G, s_img, s_lbl);
         __syncthreads();
         if (G.cls == kInterior)
             run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);

@@ -19,7 +19,10 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _require(t, name, dtypes, ndim=3):
+def _require(t, name, dtypes, ndim=3, strided=False):
+    """Type/device/rank checks.  strided: t may be a view whose layout the
+    library accepts for gathered inputs (z contiguous, x stride a whole number
+    of y rows); the library validates the strides themselves."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if t.device.type != "cuda":
@@ -28,17 +31,22 @@ def _require(t, name, dtypes, ndim=3):
         raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
     if t.dim() != ndim:
         raise ValueError(f"{name} must have {ndim} dimensions")
-    if not t.is_contiguous():
+    if not strided and not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
 
 
 def vol(t):
+    """ctaug_vol of a tensor: dense volumes pass zero strides, views their
+    element strides."""
     v = _lib.Vol()
     v.data = t.data_ptr() if t.numel() > 0 else None
     v.dtype = _DTYPES[t.dtype]
     v.reserved = 0
     for i in range(3):
         v.dim[i] = t.shape[i]
+    if t.numel() > 0 and not t.is_contiguous():
+        for i in range(3):
+            v.stride[i] = t.stride(i)
     return v
 
 
@@ -89,14 +97,14 @@ def affine_matrix(prm, in_dim, out_dim):
 
 
 def _warp(fn_name, img, M, disp, lbl, fill, label_fill, photo, out_dim, out, lbl_out, ctrl=None):
-    _require(img, "img", (torch.float32, torch.int16))
+    _require(img, "img", (torch.float32, torch.int16), strided=True)
     if out_dim is None:
         out_dim = tuple(img.shape) if out is None else tuple(out.shape)
     if out is None:
         out = torch.empty(tuple(out_dim), dtype=torch.float32, device=img.device)
     _require(out, "out", (torch.float32,))
     if lbl is not None:
-        _require(lbl, "lbl", (torch.int8,))
+        _require(lbl, "lbl", (torch.int8,), strided=True)
         if lbl_out is None:
             lbl_out = torch.empty(tuple(out.shape), dtype=torch.int8, device=img.device)
         _require(lbl_out, "lbl_out", (torch.int8,))
@@ -190,7 +198,7 @@ def warp_backward_workspace(out_dim):
 
 
 def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp):
-    _require(img, "img", (torch.float32, torch.int16))
+    _require(img, "img", (torch.float32, torch.int16), strided=True)
     _require(grad_out, "grad_out", (torch.float32,))
     dev = img.device
     g_img = torch.zeros(tuple(img.shape), dtype=torch.float32, device=dev) if want_img else None
@@ -232,7 +240,7 @@ def warp_bspline_backward(img, M, ctrl, grad_out, fill=-1000.0, want_img=True, w
                           want_ctrl=True):
     """Adjoint of warp_bspline: (grad_img, grad_M float64[12], grad_ctrl
     [3][Gx][Gy][Gz]), each None when not wanted."""
-    _require(img, "img", (torch.float32, torch.int16))
+    _require(img, "img", (torch.float32, torch.int16), strided=True)
     _require(grad_out, "grad_out", (torch.float32,))
     _require(ctrl, "ctrl", (torch.float32,), ndim=4)
     if ctrl.shape[0] != 3:

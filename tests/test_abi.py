@@ -35,13 +35,14 @@ def declared_symbols():
                                  r"(ctaug_\w+)\s*\(", text, flags=re.M)))
 
 
-def vol(dims, dtype=F32, data=FAKE, reserved=0):
+def vol(dims, dtype=F32, data=FAKE, reserved=0, stride=None):
     v = _lib.Vol()
     v.data = data
     v.dtype = dtype
     v.reserved = reserved
     for i in range(3):
         v.dim[i] = dims[i]
+        v.stride[i] = 0 if stride is None else stride[i]
     return v
 
 
@@ -188,6 +189,75 @@ def test_warp_rejects_bad_arguments(L):
     assert warp(L, img, None, M, math.nan, 0, None, out, None) == EINVAL
     assert warp(L, img, lbl, M, 0.0, 128, None, out, lout) == EINVAL
     assert warp(L, img, lbl, M, 0.0, -129, None, out, lout) == EINVAL
+
+
+# -- layouts and the kernels' 24-bit offset arithmetic --------------------------
+
+EMPTY_OUT = dict(dims=(0, 4, 4), data=None)
+
+
+def test_gather_offsets_beyond_24_bits_are_rejected(L):
+    """Input offsets are (ix ry + iy) sy + iz with 24-bit multiplies: shapes
+    whose row count (X-1) ry + Y exceeds 2^24, or whose row pitch reaches
+    2^24, are refused before anything runs (an empty output makes an accepted
+    call a no-op, so acceptance is visible without a GPU)."""
+    out = vol(**EMPTY_OUT)
+    M = mat()
+    for dims in [(2, 1 << 24, 4), (8192, 4096, 2), (1, 1, 1 << 24), (4097, 4096, 1),
+                 (2, (1 << 23) + 1, 1)]:
+        assert warp(L, vol(dims, I16), None, M, 0.0, 0, None, out, None) == ESHAPE, dims
+        lbl, lout = vol(dims, I8), vol((0, 4, 4), I8, data=None)
+        assert warp(L, vol(dims, I16), lbl, M, 0.0, 0, None, out, lout) == ESHAPE, dims
+    # just inside: X*Y = 2^24 rows, row pitch 2^24 - 1
+    for dims in [(4096, 4096, 1), (1 << 12, 1 << 12, 2), (1, 1, (1 << 24) - 1), (1, 1 << 24, 1)]:
+        assert warp(L, vol(dims, I16), None, M, 0.0, 0, None, out, None) == OK, dims
+    # a strided view: its parent's rows count (here 2^24 + 256 rows)
+    par = (1 << 12, (1 << 12) + 1, 4)
+    st = (par[1] * par[2], par[2], 1)
+    assert warp(L, vol((4096, 4096, 4), I16, stride=st), None, M, 0.0, 0, None, out,
+                None) == ESHAPE
+    assert warp(L, vol((4095, 4096, 4), I16, stride=st), None, M, 0.0, 0, None, out,
+                None) == OK
+    # the adjoints read the same image
+    r = ctypes.byref
+    big = vol((8192, 4096, 2), I16)
+    assert L.ctaug_warp_affine_backward(r(big), M, 0.0, r(vol((0, 4, 4), data=None)), None,
+                                        None, None, 0, None) == ESHAPE
+
+
+def test_strided_layouts(L):
+    """Strided views are accepted for gathered inputs only, with z contiguous
+    and the x stride a whole number of y rows."""
+    out, M = vol(**EMPTY_OUT), mat()
+    ok = [(40 * 30, 30, 1), (40 * 30 * 3, 30, 1), (0, 0, 0), (8 * 8, 8, 1)]
+    for st in ok:
+        assert warp(L, vol((8, 8, 8), I16, stride=st), None, M, 0.0, 0, None, out, None) == OK, st
+    bad = [(64, 8, 2),          # z not contiguous
+           (64, 7, 1),          # row pitch below Z
+           (60, 8, 1),          # x stride not a whole number of rows
+           (56, 8, 1),          # fewer rows per plane than Y
+           (64, 0, 1), (-64, 8, 1), (0, 8, 1)]
+    for st in bad:
+        assert warp(L, vol((8, 8, 8), I16, stride=st), None, M, 0.0, 0, None, out,
+                    None) == ESHAPE, st
+    # labels must share the image's layout
+    img = vol((8, 8, 8), I16, stride=(40 * 30, 30, 1))
+    lout = vol((0, 4, 4), I8, data=None)
+    assert warp(L, img, vol((8, 8, 8), I8, stride=(40 * 30, 30, 1)), M, 0.0, 0, None, out,
+                lout) == OK
+    assert warp(L, img, vol((8, 8, 8), I8), M, 0.0, 0, None, out, lout) == ESHAPE
+    # outputs must be dense
+    assert warp(L, vol((8, 8, 8), I16), None, M, 0.0, 0, None,
+                vol((4, 4, 4), stride=(40, 10, 1)), None) == ESHAPE
+    # an FP32 input's byte extent must fit a 32-bit buffer range
+    assert warp(L, vol((2, 2, 2), F32, stride=(1 << 30, 1 << 15, 1)), None, M, 0.0, 0, None,
+                out, None) == ESHAPE
+    assert warp(L, vol((2, 2, 2), I16, stride=(1 << 30, 1 << 15, 1)), None, M, 0.0, 0, None,
+                out, None) == OK
+    # dense-only arguments elsewhere
+    ph = photo()
+    assert L.ctaug_photometric_noise(ctypes.byref(vol((4, 4, 4), stride=(40, 10, 1))),
+                                     ctypes.byref(ph), None) == ESHAPE
 
 
 @pytest.mark.parametrize("kw", [dict(sigma=-1.0), dict(gamma=0.0), dict(gain=math.nan),

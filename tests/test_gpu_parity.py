@@ -946,3 +946,124 @@ def test_autotune_picks_a_candidate_and_results_hold():
                                      out_dim=j.out_dim)
         assert torch.equal(out, s_out)
     plan.close()
+
+
+def test_autotune_then_run_uses_the_winning_tables():
+    """After autotuning, run() (no upload) decodes tiles with the winner's
+    prefix table and job table, also when the winner was not the last
+    candidate timed (here the last one gathers 4^3 tiles directly, far
+    slower than the first)."""
+    T = _batch_jobs(n=3)
+    jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
+            for (j, M, img, lbl, out, lout) in T]
+    plan = ctaug.BatchPlan(jobs)
+    cands = [((16, 16, 16), 0, 0, 0), ((4, 4, 4), 0, -1, 0)]
+    best, times = plan.autotune(cands, reps=3)
+    assert plan.tuning() == best
+    for (j, M, img, lbl, out, lout) in T:
+        out.zero_()
+        lout.zero_()
+    plan.run()
+    for (j, M, img, lbl, out, lout) in T:
+        s_out, s_lout = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo,
+                                          out_dim=j.out_dim)
+        assert torch.equal(out, s_out) and torch.equal(lout, s_lout)
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Strided inputs (crop views) and the 24-bit offset limits
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.int16, np.float32])
+def test_strided_crop_views_match_dense_copies(dtype):
+    """A crop passed as a view of the whole scan gives the bits of the same
+    crop copied densely: single calls, batch jobs and the adjoint."""
+    parent, plbl = phantom_pair((60, 52, 48), seed=33)
+    parent = parent.astype(dtype)
+    sl = (slice(5, 45), slice(3, 43), slice(7, 39))
+    crop, clbl = np.ascontiguousarray(parent[sl]), np.ascontiguousarray(plbl[sl])
+    tp, tl = _t(parent), _t(plbl)
+    view, lview = tp[sl], tl[sl]
+    assert not view.is_contiguous()
+    rng = np.random.default_rng(34)
+    out_dim = (36, 32, 28)
+    prm = draw_affine_params(rng, AugmentRanges(), crop.shape, out_dim)
+    _, M = ctaug.affine_matrix(prm, crop.shape, out_dim)
+    ph = draw_photo(rng, AugmentRanges(), seed=3, volume_id=1)
+    o1, l1 = ctaug.warp_affine(view, M, lbl=lview, photo=ph, out_dim=out_dim)
+    o2, l2 = ctaug.warp_affine(_t(crop), M, lbl=_t(clbl), photo=ph, out_dim=out_dim)
+    assert torch.equal(o1, o2) and torch.equal(l1, l2)
+    ref, lref = oracle.warp(crop, M, out_dim, lbl=clbl, photo=ph)
+    assert np.array_equal(_np(l1), lref)
+    assert_intensity(_np(o1), ref, windowed=True, what="strided crop")
+    # batch job with strided inputs
+    o3 = torch.empty(out_dim, dtype=torch.float32, device=DEV)
+    l3 = torch.empty(out_dim, dtype=torch.int8, device=DEV)
+    plan = ctaug.BatchPlan([ctaug.make_job(view, M, o3, lview, l3, photo=ph)])
+    plan.launch()
+    assert torch.equal(o3, o1) and torch.equal(l3, l1)
+    plan.close()
+    # the adjoint reads the view
+    g = _t(rng.standard_normal(out_dim).astype(np.float32))
+    gi1, gM1 = ctaug.warp_affine_backward(view, M, g)
+    gi2, gM2 = ctaug.warp_affine_backward(_t(crop), M, g)
+    assert torch.equal(gM1, gM2)
+    r_img, r_M, _ = oracle.warp_backward(crop, M, _np(g))
+    assert_grad(_np(gi1), r_img, "strided g_img")
+    assert_grad(_np(gM1), r_M, "strided g_M")
+
+
+def test_gather_offsets_at_the_24_bit_limits():
+    """Inputs at the largest row count (X*Y = 2^24) and row pitch (2^24 - 1)
+    the 24-bit offset arithmetic admits, sampled up to their last voxel."""
+    # 2048 x 8192 x 2: X*Y = 2^24 rows
+    dims = (2048, 8192, 2)
+    rng = np.random.default_rng(35)
+    img = rng.integers(-1000, 1500, size=dims, dtype=np.int16)
+    lbl = rng.integers(0, 6, size=dims, dtype=np.int8)
+    out_dim = (24, 24, 8)
+    M = np.array([2047.0 / 23, 0.0, 0.0, 0.0,
+                  0.0, 8191.0 / 23, 0.01, 0.0,
+                  0.0, 0.0, 1.0 / 7, 0.0], np.float32)
+    out, lout = ctaug.warp_affine(_t(img), M, lbl=_t(lbl), out_dim=out_dim)
+    ref, lref = oracle.warp(img, M, out_dim, lbl=lbl)
+    assert np.array_equal(_np(lout), lref)
+    assert_intensity(_np(out), ref, windowed=False, what="X*Y = 2^24")
+    # 1 x 1 x (2^24 - 1): the largest row pitch
+    n = (1 << 24) - 1
+    img2 = rng.integers(-1000, 1500, size=(1, 1, n), dtype=np.int16)
+    M2 = np.array([0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1.0, n - 1 - 63], np.float32)
+    out2, _ = ctaug.warp_affine(_t(img2), M2, out_dim=(1, 1, 64))
+    got = _np(out2)[0, 0]
+    assert np.array_equal(got, img2[0, 0, n - 64:].astype(np.float32))
+
+
+@pytest.mark.parametrize("scale", [1.0, 3.5])
+def test_affine_backward_nonfinite_gradients(scale):
+    """NaN and infinite upstream gradients propagate to exactly the image
+    cells the oracle's FP64 adjoint gives them (every in-volume corner of the
+    voxel's cell), on the fixed-point LDS path and on the direct path (large
+    footprints); other cells keep the gradient bar."""
+    dims = (40, 36, 32)
+    img, _ = phantom_pair(dims, seed=21)
+    img = img.astype(np.float32)
+    rng = np.random.default_rng(22)
+    ranges = AugmentRanges(scale=(scale, scale), disp=(0.0, 0.0, 0.0))
+    prm = draw_affine_params(rng, ranges, dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    g = rng.standard_normal(dims).astype(np.float32)
+    flat = g.reshape(-1)
+    centre = ((np.indices(dims) - (np.array(dims)[:, None, None, None] - 1) / 2) ** 2).sum(0)
+    inner = np.flatnonzero(centre.reshape(-1) < 5.0 ** 2)   # q stays inside
+    pick = rng.choice(inner, size=6, replace=False)
+    flat[pick[:4]] = np.nan
+    flat[pick[4:]] = np.inf
+    g_img, g_M = ctaug.warp_affine_backward(_t(img), M, _t(g))
+    r_img, r_M, _ = oracle.warp_backward(img, M, g)
+    gi = _np(g_img)
+    assert np.isnan(r_img).any() and np.array_equal(np.isnan(gi), np.isnan(r_img))
+    assert np.array_equal(np.isinf(gi), np.isinf(r_img))
+    fin = np.isfinite(r_img)
+    assert_grad(gi[fin], r_img[fin], "finite cells")
+    assert np.isnan(_np(g_M)).all() and np.isnan(r_M).all()

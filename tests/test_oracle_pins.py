@@ -634,11 +634,27 @@ def test_gain_offset_gamma_closed_forms():
     V = np.linspace(-1500, 1800, 331)
     ph = PhotoParams(gain=1.0625, offset=-12.5, sigma=0.0, window=False)
     np.testing.assert_array_equal(oracle.photometric(V, ph), 1.0625 * V - 12.5)
-    ph = PhotoParams(gain=1.0, offset=0.0, win_lo=-1000, win_hi=1000, gamma=0.8, window=True)
-    t = np.clip((V + 1000) / 2000, 0, 1)
-    np.testing.assert_allclose(oracle.photometric(V, ph), t ** np.float32(0.8), rtol=1e-15, atol=0)
-    ph.gamma = 1.25
-    assert oracle.photometric(np.array([-1000.0]), ph)[0] == 0.0
+    # window then gamma: values whose windowed t is a power of two, with
+    # exponents exact in FP32, have exact closed forms t^gamma
+    cases = [  # (v in HU, gamma, t^gamma) on the window [-1000, 1000]
+        (-500.0, 0.5, 0.5),          # t = 1/4
+        (-875.0, 1.25, 1.0 / 32),    # t = 1/16
+        (125.0, 0.5, 0.75),          # t = 9/16
+        (-500.0, 1.5, 0.125),        # t = 1/4
+        (-1000.0 + 2000.0 / 1024, 0.8, 2.0 ** (-10 * float(np.float32(0.8)))),
+        (-1000.0, 0.8, 0.0),         # t = 0: 0^gamma = 0
+        (-2500.0, 1.25, 0.0),        # below the window
+        (1000.0, 0.8, 1.0),          # t = 1
+        (4000.0, 0.5, 1.0),          # above the window
+    ]
+    for v, gam, expect in cases:
+        ph = PhotoParams(gain=1.0, offset=0.0, win_lo=-1000, win_hi=1000, gamma=gam, window=True)
+        got = oracle.photometric(np.array([v]), ph)[0]
+        assert got == pytest.approx(expect, rel=1e-15, abs=0), (v, gam)
+    # gain and offset act before the window: V = 200 with gain 1/2 and offset
+    # -600 is v = -500, t = 1/4
+    ph = PhotoParams(gain=0.5, offset=-600.0, win_lo=-1000, win_hi=1000, gamma=0.5, window=True)
+    assert oracle.photometric(np.array([200.0]), ph)[0] == 0.5
 
 
 def test_noise_is_additive_gaussian_per_voxel():
