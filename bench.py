@@ -412,7 +412,7 @@ def run_c4(dev, stream, reps):
         side.fork()
         for k in range(len(jobs)):
             i = k % len(side)
-            r = L.ctaug_warp_affine_backward(ctypes.byref(vi[k]), Mc[k], jobs[k].fill,
+            r = L.ctaug_warp_affine_backward(ctypes.byref(vi[k]), Mc[k], jobs[k].fill, None,
                                              ctypes.byref(vg[k]), ctypes.byref(vgi[k]),
                                              ctypes.c_void_p(g_M[k].data_ptr()),
                                              ctypes.c_void_p(ws[i].data_ptr()), ws_bytes,
@@ -474,7 +474,8 @@ def run_c5(dev, stream, reps):
         for k, j in enumerate(jobs):
             i = k % len(side)
             r = L.ctaug_warp_bspline_backward(ctypes.byref(vi[k]), Mc[k], P(cs[k].data_ptr()), G,
-                                              j.fill, ctypes.byref(vg[k]), ctypes.byref(vgi[k]),
+                                              j.fill, None, ctypes.byref(vg[k]),
+                                              ctypes.byref(vgi[k]),
                                               P(g_Ms[k].data_ptr()), P(g_cs[k].data_ptr()),
                                               P(ws[i].data_ptr()), ws_bytes, side.handle(i))
             assert r == 0

@@ -228,28 +228,40 @@ ctaug_status ctaug_box_muller(const uint32_t *words, int64_t npairs, float *out,
  * out_dim (0 for an empty volume, or on bad dims). */
 size_t ctaug_warp_backward_workspace(const int64_t out_dim[3]);
 
-/* Adjoint of the affine warp's image path (photometrics excluded).  With
- * weights w_c(p) of the in-volume corners c of the cell floor(q(p)):
- *   grad_img[c] += sum_p w_c(p) grad_out(p)        (FP32 atomics; accumulates)
- *   grad_M[i][j] = sum_p grad_out(p) dV/dq_i(p) [x,y,z,1]_j   (overwritten)
+/* Adjoint of the affine warp, including the photometric chain when it is
+ * differentiable.  With photo (NULL = none) the forward output is
+ * gain * V' + offset + sigma * n, V' = 0 on the occluded slab and V' = V
+ * elsewhere (ctaug_photo without WINDOW: affine in V, the noise a constant),
+ * so the gradient reaching V is g(p) = gain * grad_out(p) off the slab and 0
+ * on it (computed in FP32 in the kernel); photo == NULL gives
+ * g = grad_out.  With weights w_c(p) of the in-volume corners c of the cell
+ * floor(q(p)):
+ *   grad_img[c] += sum_p w_c(p) g(p)              (accumulates; see below)
+ *   grad_M[i][j] = sum_p g(p) dV/dq_i(p) [x,y,z,1]_j   (overwritten)
  * dV/dq is the derivative of the interpolant on the cell floor(q) (fill
  * corners included, i.e. the right derivative at integer q); samples outside
- * (-1, n) contribute nothing.  img_in: device F32/I16; grad_out: device F32
- * with the output dims; grad_img: device F32 with img_in's dims, or NULL;
- * grad_M: device double[12], or NULL.  ws: device workspace of at least
- * ctaug_warp_backward_workspace(out dims) bytes (required when grad_M is
- * given).  grad_M is reduced deterministically in FP64.
+ * (-1, n) contribute nothing.  The sums of grad_img are exact within each
+ * output tile (64-bit fixed point) and tiles meet in FP32 atomics; a tile
+ * with a non-finite g adds per corner in FP32 (NaN and infinities reach
+ * every in-volume corner of the voxel's cell, as 0 * NaN = NaN).
+ * img_in: device F32/I16 (may be strided); photo: host, WINDOW not allowed
+ * (EINVAL); grad_out: device F32 with the output dims; grad_img: device F32
+ * with img_in's dims (dense), or NULL; grad_M: device double[12], or NULL.
+ * ws: device workspace of at least ctaug_warp_backward_workspace(out dims)
+ * bytes (required when grad_M is given).  grad_M is reduced
+ * deterministically in FP64.
  * Errors: EINVAL, EDTYPE, ESHAPE, EWORKSPACE, EHIP. */
 ctaug_status ctaug_warp_affine_backward(const ctaug_vol *img_in, const float M[12], float fill,
-                                        const ctaug_vol *grad_out, ctaug_vol *grad_img,
-                                        double *grad_M, void *ws, size_t ws_bytes,
-                                        void *stream);
+                                        const ctaug_photo *photo, const ctaug_vol *grad_out,
+                                        ctaug_vol *grad_img, double *grad_M, void *ws,
+                                        size_t ws_bytes, void *stream);
 
-/* Adjoint of ctaug_warp_displacement's image path: as above, plus
- * grad_disp[i](p) = grad_out(p) dV/dq_i(p) (device float SoA [3][Xo][Yo][Zo],
+/* Adjoint of ctaug_warp_displacement: as above (photo likewise), plus
+ * grad_disp[i](p) = g(p) dV/dq_i(p) (device float SoA [3][Xo][Yo][Zo],
  * overwritten, or NULL). */
 ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in, const float M[12],
                                               const float *disp, float fill,
+                                              const ctaug_photo *photo,
                                               const ctaug_vol *grad_out, ctaug_vol *grad_img,
                                               double *grad_M, float *grad_disp, void *ws,
                                               size_t ws_bytes, void *stream);
@@ -287,9 +299,10 @@ ctaug_status ctaug_warp_bspline(const ctaug_vol *img_in, const ctaug_vol *lbl_in
 /* Workspace bytes for ctaug_warp_bspline_backward (0 on bad arguments). */
 size_t ctaug_warp_bspline_backward_workspace(const int64_t out_dim[3], const int64_t G[3]);
 
-/* Adjoint of ctaug_warp_bspline's image path: grad_img and grad_M as in
- * ctaug_warp_affine_backward (q now includes the spline displacement), and
- *   grad_ctrl = B^T grad_disp,  grad_disp[i](p) = grad_out(p) dV/dq_i(p)
+/* Adjoint of ctaug_warp_bspline: grad_img and grad_M as in
+ * ctaug_warp_affine_backward (photo likewise; q now includes the spline
+ * displacement), and
+ *   grad_ctrl = B^T grad_disp,  grad_disp[i](p) = g(p) dV/dq_i(p)
  * (device float [3][Gx][Gy][Gz], overwritten, or NULL): the gradient with
  * respect to the control grid, without a dense field in memory when the
  * grid has at most 2048 entries and no 8 x 8 x 16 output tile touches more
@@ -302,6 +315,7 @@ size_t ctaug_warp_bspline_backward_workspace(const int64_t out_dim[3], const int
  * ESHAPE (dims mismatch, bad grid), EWORKSPACE, EHIP. */
 ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, const float M[12],
                                          const float *ctrl, const int64_t G[3], float fill,
+                                         const ctaug_photo *photo,
                                          const ctaug_vol *grad_out, ctaug_vol *grad_img,
                                          double *grad_M, float *grad_ctrl, void *ws,
                                          size_t ws_bytes, void *stream);

@@ -60,6 +60,8 @@ def _declare(L):
     L.orc_gauss_range.restype = None
     L.orc_photometric.argtypes = [_p, _i64, _p, _int, _u64, _u32, _p, _i64, _p]
     L.orc_photometric.restype = _int
+    L.orc_photometric_adjoint.argtypes = [_p, _i64, _p, _int, _p, _i64, _p]
+    L.orc_photometric_adjoint.restype = _int
     L.orc_affine_matrix.argtypes = [_p, _p, _p, _p]
     L.orc_affine_matrix.restype = _int
     L.orc_warp.argtypes = [_p, _p, _p, _p, _p, _int, _p, _dbl, _int, _p, _int, _u64, _u32, _p,
@@ -155,6 +157,19 @@ def photometric(vin, photo):
     return out.reshape(np.shape(vin))
 
 
+def photometric_adjoint(g, photo):
+    """Adjoint of the photometric chain without window: gain * g off the
+    occluded slab, 0 on it (z = index mod the last axis)."""
+    gv = _c(g, np.float64).ravel()
+    out = np.empty_like(gv)
+    ph = _photo6(photo)
+    occ = _occ(photo)
+    Z = int(np.shape(g)[-1]) if np.ndim(g) else 1
+    _check(lib().orc_photometric_adjoint(_ptr(gv), gv.size, _ptr(ph), int(bool(photo.window)),
+                                         _ptr(occ), Z, _ptr(out)))
+    return out.reshape(np.shape(g))
+
+
 # -- transform ------------------------------------------------------------
 
 def affine_matrix(prm, in_dim, out_dim):
@@ -224,12 +239,13 @@ def warp_points(img, M, out_dim, idx, lbl=None, disp=None, fill=-1000.0, label_f
 
 
 def warp_backward(img, M, g, disp=None, fill=-1000.0, exact=False, want_img=True, want_M=True,
-                  want_u=False):
-    """Adjoint of the warp.  Returns (g_img float64 [in dims] or None,
-    g_M float64 [12] or None, g_u float64 [3][out dims] or None)."""
+                  want_u=False, photo=None):
+    """Adjoint of the warp (after the adjoint of the photometric chain
+    `photo`, without window, when given).  Returns (g_img float64 [in dims]
+    or None, g_M float64 [12] or None, g_u float64 [3][out dims] or None)."""
     img64 = _c(img, np.float64)
     in_dim = _dims(img64.shape)
-    g64 = _c(g, np.float64)
+    g64 = _c(g, np.float64) if photo is None else photometric_adjoint(g, photo)
     od = _dims(g64.shape)
     Mf = np.asarray(M, dtype=np.float32)
     Md = np.asarray(M, dtype=np.float64)

@@ -193,6 +193,22 @@ int orc_photometric(const double *vin, int64_t n, const double *photo, int windo
     return ORC_OK;
 }
 
+/* Adjoint of the photometric chain without the window (an addition; the   */
+/* paper has no gradients).  Off the window, out = gain * V' + offset +      */
+/* sigma * n with V' = 0 on the occluded slab and V' = V elsewhere: affine   */
+/* in V, the noise a constant.  So dout/dV = gain off the slab and 0 on it,  */
+/* and g_V(p) = gain * g(p) or 0.  The window clamp and gamma are not        */
+/* differentiated (EINVAL).  photo, occ, Z as orc_photometric.               */
+int orc_photometric_adjoint(const double *g, int64_t n, const double *photo, int window,
+                            const double *occ, int64_t Z, double *g_V)
+{
+    if (!g || !g_V || !photo || n < 0 || window || (occ && Z <= 0))
+        return ORC_EINVAL;
+    for (int64_t v = 0; v < n; ++v)
+        g_V[v] = occluded(occ, occ ? v % Z : 0) ? 0.0 : photo[0] * g[v];
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Transform sampling (Sec. GPU-AUG, first paragraph and footnote; crop from */
 /* Sec. Pre- and post-processing).                                           */

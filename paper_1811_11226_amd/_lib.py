@@ -79,13 +79,14 @@ SIGNATURES = {
                          _P, _P]),
     "ctaug_box_muller": (_S, [_P, ctypes.c_int64, _P, _P]),
     "ctaug_warp_backward_workspace": (ctypes.c_size_t, [_PI64]),
-    "ctaug_warp_affine_backward": (_S, [_PV, _PF, ctypes.c_float, _PV, _PV, _P, _P,
-                                        ctypes.c_size_t, _P]),
-    "ctaug_warp_displacement_backward": (_S, [_PV, _PF, _P, ctypes.c_float, _PV, _PV, _P, _P,
-                                              _P, ctypes.c_size_t, _P]),
+    "ctaug_warp_affine_backward": (_S, [_PV, _PF, ctypes.c_float, ctypes.POINTER(Photo), _PV,
+                                        _PV, _P, _P, ctypes.c_size_t, _P]),
+    "ctaug_warp_displacement_backward": (_S, [_PV, _PF, _P, ctypes.c_float, ctypes.POINTER(Photo),
+                                              _PV, _PV, _P, _P, _P, ctypes.c_size_t, _P]),
     "ctaug_warp_bspline_backward_workspace": (ctypes.c_size_t, [_PI64, _PI64]),
-    "ctaug_warp_bspline_backward": (_S, [_PV, _PF, _P, _PI64, ctypes.c_float, _PV, _PV, _P, _P,
-                                         _P, ctypes.c_size_t, _P]),
+    "ctaug_warp_bspline_backward": (_S, [_PV, _PF, _P, _PI64, ctypes.c_float,
+                                         ctypes.POINTER(Photo), _PV, _PV, _P, _P, _P,
+                                         ctypes.c_size_t, _P]),
     "ctaug_bspline_upsample": (_S, [_P, _PI64, _PI64, _P, _P]),
     "ctaug_bspline_adjoint_workspace": (ctypes.c_size_t, [_PI64, _PI64]),
     "ctaug_bspline_upsample_adjoint": (_S, [_P, _PI64, _PI64, _P, _P, ctypes.c_size_t, _P]),

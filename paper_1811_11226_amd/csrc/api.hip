@@ -512,8 +512,19 @@ extern "C" size_t ctaug_warp_backward_workspace(const int64_t out_dim[3])
     return (size_t)bwd_partial_rows(out_dim[0], out_dim[1], out_dim[2]) * 12 * sizeof(double);
 }
 
+// The backward passes differentiate the photometric chain only without the
+// window (affine in the sampled value).
+static ctaug_status check_photo_adjoint(const ctaug_photo *photo)
+{
+    const ctaug_status st = check_photo(photo);
+    if (st != CTAUG_OK)
+        return st;
+    return photo && (photo->flags & CTAUG_PHOTO_WINDOW) ? CTAUG_EINVAL : CTAUG_OK;
+}
+
 static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], const float *disp,
-                                  bool need_disp, float fill, const ctaug_vol *grad_out,
+                                  bool need_disp, float fill, const ctaug_photo *photo,
+                                  const ctaug_vol *grad_out,
                                   ctaug_vol *grad_img, double *grad_M, float *grad_disp, void *ws,
                                   size_t ws_bytes, void *stream)
 {
@@ -530,6 +541,8 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
     }
     if (need_disp && grad_disp && 3 * nelem(grad_out->dim) > kMaxElems)
         return CTAUG_ESHAPE;
+    if ((st = check_photo_adjoint(photo)) != CTAUG_OK)
+        return st;
     if (grad_M) {
         const size_t need = ctaug_warp_backward_workspace(grad_out->dim);
         if (need > 0 && (!ws || ws_bytes < need))
@@ -538,7 +551,7 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
     FwdJob J;
     // the gradient volume plays the part of the forward output (dims only)
     ctaug_vol out_like = *grad_out;
-    st = make_job(img_in, nullptr, M, disp, need_disp, fill, 0, nullptr, &out_like, nullptr,
+    st = make_job(img_in, nullptr, M, disp, need_disp, fill, 0, photo, &out_like, nullptr,
                   kDefaultTiling, J);
     if (st != CTAUG_OK)
         return st;
@@ -553,23 +566,25 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
 }
 
 extern "C" ctaug_status ctaug_warp_affine_backward(const ctaug_vol *img_in, const float M[12],
-                                                   float fill, const ctaug_vol *grad_out,
-                                                   ctaug_vol *grad_img, double *grad_M, void *ws,
-                                                   size_t ws_bytes, void *stream)
+                                                   float fill, const ctaug_photo *photo,
+                                                   const ctaug_vol *grad_out, ctaug_vol *grad_img,
+                                                   double *grad_M, void *ws, size_t ws_bytes,
+                                                   void *stream)
 {
-    return backward_impl(img_in, M, nullptr, false, fill, grad_out, grad_img, grad_M, nullptr, ws,
-                         ws_bytes, stream);
+    return backward_impl(img_in, M, nullptr, false, fill, photo, grad_out, grad_img, grad_M,
+                         nullptr, ws, ws_bytes, stream);
 }
 
 extern "C" ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in,
                                                          const float M[12], const float *disp,
-                                                         float fill, const ctaug_vol *grad_out,
+                                                         float fill, const ctaug_photo *photo,
+                                                         const ctaug_vol *grad_out,
                                                          ctaug_vol *grad_img, double *grad_M,
                                                          float *grad_disp, void *ws,
                                                          size_t ws_bytes, void *stream)
 {
-    return backward_impl(img_in, M, disp, true, fill, grad_out, grad_img, grad_M, grad_disp, ws,
-                         ws_bytes, stream);
+    return backward_impl(img_in, M, disp, true, fill, photo, grad_out, grad_img, grad_M,
+                         grad_disp, ws, ws_bytes, stream);
 }
 
 // Workspace of ctaug_warp_bspline_backward: grad_M partials, then either the
@@ -594,7 +609,8 @@ extern "C" size_t ctaug_warp_bspline_backward_workspace(const int64_t out_dim[3]
 
 extern "C" ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, const float M[12],
                                                     const float *ctrl, const int64_t G[3],
-                                                    float fill, const ctaug_vol *grad_out,
+                                                    float fill, const ctaug_photo *photo,
+                                                    const ctaug_vol *grad_out,
                                                     ctaug_vol *grad_img, double *grad_M,
                                                     float *grad_ctrl, void *ws, size_t ws_bytes,
                                                     void *stream)
@@ -614,6 +630,8 @@ extern "C" ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, con
         return CTAUG_EINVAL;
     if (!grid_valid(G))
         return CTAUG_ESHAPE;
+    if ((st = check_photo_adjoint(photo)) != CTAUG_OK)
+        return st;
     const int64_t *od = grad_out->dim;
     const BsplineGeom B = bspline_geom(G, od);
     // fused kernel (field evaluated in the adjoint), or the dense route
@@ -625,7 +643,7 @@ extern "C" ctaug_status ctaug_warp_bspline_backward(const ctaug_vol *img_in, con
         return CTAUG_EWORKSPACE;
     FwdJob J;
     ctaug_vol out_like = *grad_out;    // the gradient plays the part of the output (dims only)
-    st = make_job(img_in, nullptr, M, nullptr, false, fill, 0, nullptr, &out_like, nullptr,
+    st = make_job(img_in, nullptr, M, nullptr, false, fill, 0, photo, &out_like, nullptr,
                   kDefaultTiling, J);
     if (st != CTAUG_OK)
         return st;

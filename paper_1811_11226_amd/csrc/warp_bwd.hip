@@ -1,7 +1,9 @@
 // warp_bwd.hip -- adjoint kernels of the warp (gfx950).
 //
 // Persistent workgroups over 8 x 8 x 16 output tiles.  For every output voxel
-// the forward coordinate and cell are recomputed; the eight corner values
+// the upstream gradient is taken through the adjoint of the photometric chain
+// (gain, zero on the occluded slab), the forward coordinate and cell are
+// recomputed; the eight corner values
 // (staged in LDS, fill substituted outside the volume) give the derivative of
 // the trilinear interpolant on that cell, dV/dq.  Then
 //   grad_img[c] += w_c * g          summed per tile in 64-bit fixed point in
@@ -342,7 +344,16 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                 qv[k][1] = qy;
                 qv[k][2] = qz;
                 gd[k] = !empty_in && in_guard(qx, qy, qz, J.nx, J.ny, J.nz);
-                gpk[k] = g[v];
+                // adjoint of the photometric chain without window: the output
+                // is gain * V + offset + sigma * n off the occluded slab and
+                // does not depend on V on it
+                float gv = g[v];
+                if (J.flags & kFlagPhoto) {
+                    gv = J.gain * gv;
+                    if ((J.flags & kFlagOcclude) && zf >= J.occ_lo && zf <= J.occ_hi)
+                        gv = 0.0f;
+                }
+                gpk[k] = gv;
             }
         }
         TileGeom G;

@@ -197,7 +197,7 @@ def warp_backward_workspace(out_dim):
     return int(_lib.load().ctaug_warp_backward_workspace(d))
 
 
-def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp):
+def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp, photo=None):
     _require(img, "img", (torch.float32, torch.int16), strided=True)
     _require(grad_out, "grad_out", (torch.float32,))
     dev = img.device
@@ -207,11 +207,13 @@ def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp):
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if want_M else None
     vi, vg = vol(img), vol(grad_out)
     vgi = vol(g_img) if want_img else None
+    ph = make_photo(photo)
     L = _lib.load()
     p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
     if disp is None:
-        st = L.ctaug_warp_affine_backward(ctypes.byref(vi), _M32(M), float(fill), ctypes.byref(vg),
-                                          _ref(vgi), p(g_M), p(ws), ws_bytes, _stream())
+        st = L.ctaug_warp_affine_backward(ctypes.byref(vi), _M32(M), float(fill), _ref(ph),
+                                          ctypes.byref(vg), _ref(vgi), p(g_M), p(ws), ws_bytes,
+                                          _stream())
         _lib.check(st, "ctaug_warp_affine_backward")
         return g_img, g_M
     _require(disp, "disp", (torch.float32,), ndim=4)
@@ -219,25 +221,28 @@ def _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp):
         raise ValueError(f"disp: expected {(3,) + tuple(grad_out.shape)}, got {tuple(disp.shape)}")
     g_disp = torch.empty_like(disp) if want_disp else None
     st = L.ctaug_warp_displacement_backward(ctypes.byref(vi), _M32(M), p(disp), float(fill),
-                                            ctypes.byref(vg), _ref(vgi), p(g_M), p(g_disp), p(ws),
-                                            ws_bytes, _stream())
+                                            _ref(ph), ctypes.byref(vg), _ref(vgi), p(g_M),
+                                            p(g_disp), p(ws), ws_bytes, _stream())
     _lib.check(st, "ctaug_warp_displacement_backward")
     return g_img, g_M, g_disp
 
 
-def warp_affine_backward(img, M, grad_out, fill=-1000.0, want_img=True, want_M=True):
-    """(grad_img float32 or None, grad_M float64[12] or None)."""
-    return _backward(img, M, grad_out, None, fill, want_img, want_M, False)
+def warp_affine_backward(img, M, grad_out, fill=-1000.0, want_img=True, want_M=True,
+                         photo=None):
+    """(grad_img float32 or None, grad_M float64[12] or None).  photo: the
+    forward's photometric parameters without window (gain, offset, noise,
+    occlusion), whose adjoint the kernel applies; None = none."""
+    return _backward(img, M, grad_out, None, fill, want_img, want_M, False, photo)
 
 
 def warp_displacement_backward(img, M, disp, grad_out, fill=-1000.0, want_img=True,
-                               want_M=True, want_disp=True):
+                               want_M=True, want_disp=True, photo=None):
     """(grad_img, grad_M, grad_disp)."""
-    return _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp)
+    return _backward(img, M, grad_out, disp, fill, want_img, want_M, want_disp, photo)
 
 
 def warp_bspline_backward(img, M, ctrl, grad_out, fill=-1000.0, want_img=True, want_M=True,
-                          want_ctrl=True):
+                          want_ctrl=True, photo=None):
     """Adjoint of warp_bspline: (grad_img, grad_M float64[12], grad_ctrl
     [3][Gx][Gy][Gz]), each None when not wanted."""
     _require(img, "img", (torch.float32, torch.int16), strided=True)
@@ -256,10 +261,11 @@ def warp_bspline_backward(img, M, ctrl, grad_out, fill=-1000.0, want_img=True, w
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
     vi, vg = vol(img), vol(grad_out)
     vgi = vol(g_img) if want_img else None
+    ph = make_photo(photo)
     p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
     st = L.ctaug_warp_bspline_backward(ctypes.byref(vi), _M32(M), p(ctrl), G, float(fill),
-                                       ctypes.byref(vg), _ref(vgi), p(g_M), p(g_ctrl), p(ws),
-                                       ws_bytes, _stream())
+                                       _ref(ph), ctypes.byref(vg), _ref(vgi), p(g_M), p(g_ctrl),
+                                       p(ws), ws_bytes, _stream())
     _lib.check(st, "ctaug_warp_bspline_backward")
     return g_img, g_M, g_ctrl
 

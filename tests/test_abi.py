@@ -221,7 +221,7 @@ def test_gather_offsets_beyond_24_bits_are_rejected(L):
     # the adjoints read the same image
     r = ctypes.byref
     big = vol((8192, 4096, 2), I16)
-    assert L.ctaug_warp_affine_backward(r(big), M, 0.0, r(vol((0, 4, 4), data=None)), None,
+    assert L.ctaug_warp_affine_backward(r(big), M, 0.0, None, r(vol((0, 4, 4), data=None)), None,
                                         None, None, 0, None) == ESHAPE
 
 
@@ -308,16 +308,26 @@ def test_backward_workspace_and_validation(L):
     img, g = vol((8, 8, 8)), vol((64, 64, 64))
     gM = FAKE
     r = ctypes.byref
-    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(g), None, gM, None, 0,
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, None, r(g), None, gM, None, 0,
                                         None) == EWORKSPACE
-    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(g), None, gM, FAKE, ws - 8,
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, None, r(g), None, gM, FAKE, ws - 8,
                                         None) == EWORKSPACE
-    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(g), r(vol((8, 8, 9))), None, None,
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, None, r(g), r(vol((8, 8, 9))), None, None,
                                         0, None) == ESHAPE
-    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(vol((64, 64, 64), I16)), None, gM,
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, None, r(vol((64, 64, 64), I16)), None, gM,
                                         FAKE, ws, None) == EDTYPE
-    assert L.ctaug_warp_displacement_backward(r(img), mat(), None, 0.0, r(g), None, gM, None,
+    assert L.ctaug_warp_displacement_backward(r(img), mat(), None, 0.0, None, r(g), None, gM, None,
                                               FAKE, ws, None) == EINVAL
+    # the photometric adjoint: the windowed chain is not differentiated, and
+    # parameters are validated as in the forward
+    out0 = vol((0, 4, 4), data=None)
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(photo(flags=1)), r(out0), None,
+                                        None, None, 0, None) == EINVAL
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(photo(gain=math.nan)), r(out0),
+                                        None, None, None, 0, None) == EINVAL
+    assert L.ctaug_warp_affine_backward(r(img), mat(), 0.0, r(photo(flags=2, occ_lo=1.0,
+                                                                     occ_hi=3.0)),
+                                        r(out0), None, None, None, 0, None) == OK
 
 
 def test_bspline_validation(L):
@@ -377,7 +387,7 @@ def test_fused_bspline_backward_workspace_and_validation(L):
     need = L.ctaug_warp_bspline_backward_workspace(od, g8)
 
     def call(ctrl=FAKE, G=g8, gimg=None, gM=FAKE, gc=FAKE, ws=FAKE, nbytes=need, gout=g):
-        return L.ctaug_warp_bspline_backward(r(img), mat(), ctrl, G, 0.0, r(gout),
+        return L.ctaug_warp_bspline_backward(r(img), mat(), ctrl, G, 0.0, None, r(gout),
                                              r(gimg) if gimg is not None else None, gM, gc, ws,
                                              nbytes, None)
 

@@ -664,14 +664,46 @@ def test_autograd_affine_with_photometrics():
     ref, _ = oracle.warp(img_np, M32, dims, photo=ph)
     assert_intensity(_np(out), ref, windowed=False, what="autograd forward")
     (out * _t(g)).sum().backward()
-    z = np.arange(dims[2], dtype=np.float32)
-    keep = (z < np.float32(ph.occ_lo)) | (z > np.float32(ph.occ_hi))
-    g_eff = (g.astype(np.float64) * float(np.float32(ph.gain)) * keep).astype(np.float32)
-    r_img, r_M, _ = oracle.warp_backward(img_np, M32, g_eff)
+    r_img, r_M, _ = oracle.warp_backward(img_np, M32, g, photo=ph)
     assert_grad(_np(img.grad), r_img, "g_img")
     assert_grad(M.grad.numpy(), r_M, "g_M")
-    with pytest.raises(ValueError):
-        ag.warp_affine(img, M, photo=draw_photo(rng, AugmentRanges(), seed=1, volume_id=0))
+    # the windowed chain is refused by the library's adjoint
+    out = ag.warp_affine(img, M, photo=draw_photo(rng, AugmentRanges(), seed=1, volume_id=0))
+    with pytest.raises(ctaug._lib.CtaugError):
+        out.sum().backward()
+
+
+@pytest.mark.parametrize("kind", ["affine", "displacement", "bspline"])
+def test_photometric_adjoint_in_the_kernels(kind):
+    """The adjoint calls apply the photometric chain's adjoint (gain, zero on
+    the occluded slab) themselves: against the oracle's adjoint of the same
+    chain, for the three warps."""
+    rng = np.random.default_rng(35)
+    dims = (30, 26, 34)
+    img_np, _ = phantom_pair(dims, seed=9)
+    img_np = img_np.astype(np.float32)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    _, M = ctaug.affine_matrix(prm, dims, dims)
+    ph = draw_photo(rng, AugmentRanges(window=False, gain=(0.8, 0.8)), seed=4, volume_id=2)
+    ph.occlude, ph.occ_lo, ph.occ_hi = True, 5.5, 14.0
+    g = rng.standard_normal(dims).astype(np.float32)
+    if kind == "affine":
+        g_img, g_M = ctaug.warp_affine_backward(_t(img_np), M, _t(g), photo=ph)
+        r_img, r_M, _ = oracle.warp_backward(img_np, M, g, photo=ph)
+    elif kind == "displacement":
+        disp = rng.uniform(-2.0, 2.0, (3,) + dims).astype(np.float32)
+        g_img, g_M, g_d = ctaug.warp_displacement_backward(_t(img_np), M, _t(disp), _t(g),
+                                                            photo=ph)
+        r_img, r_M, r_u = oracle.warp_backward(img_np, M, g, disp=disp, photo=ph, want_u=True)
+        assert_grad(_np(g_d), r_u, "g_disp")
+    else:
+        C = (2.0 * rng.standard_normal((3, 6, 6, 6))).astype(np.float32)
+        g_img, g_M, g_c = ctaug.warp_bspline_backward(_t(img_np), M, _t(C), _t(g), photo=ph)
+        u = oracle.bspline_upsample_f32(C, dims)
+        r_img, r_M, r_u = oracle.warp_backward(img_np, M, g, disp=u, photo=ph, want_u=True)
+        assert_grad(_np(g_c), oracle.bspline_adjoint(r_u, (6, 6, 6)), "g_ctrl")
+    assert_grad(_np(g_img), r_img, f"{kind} g_img")
+    assert_grad(_np(g_M), r_M, f"{kind} g_M")
 
 
 def test_autograd_affine_and_nonrigid_chain():

@@ -372,6 +372,44 @@ def test_image_gradient_finite_differences():
         assert g_img[c] == pytest.approx(fd, rel=1e-9, abs=1e-9)
 
 
+def test_photometric_adjoint_finite_differences():
+    """The adjoint with the photometric chain (gain, offset, noise and an
+    occluded slab, no window): FD of the noisy, occluded forward in the image
+    and in M against the adjoint of gain * g off the slab."""
+    rng = np.random.default_rng(16)
+    dims = (16, 16, 16)
+    img = _rand_img(rng, dims)
+    prm = draw_affine_params(rng, AugmentRanges(), dims, dims)
+    M = oracle.affine_matrix(prm, dims, dims)
+    ph = PhotoParams(gain=1.0625, offset=-7.5, sigma=10.0, window=False, seed=44, volume_id=3,
+                     occlude=True, occ_lo=4.0, occ_hi=9.5)
+    g = rng.standard_normal(dims)
+    g_img, g_M, _ = oracle.warp_backward(img, M, g, fill=FILL, exact=True, photo=ph)
+    gv = oracle.photometric_adjoint(g, ph)
+    z = np.arange(dims[2])
+    assert not gv[:, :, (z >= 4) & (z <= 9)].any()
+    np.testing.assert_array_equal(gv[:, :, :4], 1.0625 * g[:, :, :4])
+    for c in [(8, 8, 8), (3, 12, 7)]:
+        ip, im = img.copy(), img.copy()
+        ip[c] += 1.0
+        im[c] -= 1.0
+        vp, _ = oracle.warp(ip, M, dims, fill=FILL, exact=True, photo=ph)
+        vm, _ = oracle.warp(im, M, dims, fill=FILL, exact=True, photo=ph)
+        fd = (np.vdot(vp, g) - np.vdot(vm, g)) / 2.0
+        assert g_img[c] == pytest.approx(fd, rel=1e-9, abs=1e-9)
+    h = 1e-6
+    for k in (0, 5, 11):
+        Mp, Mm = M.copy(), M.copy()
+        Mp[k] += h
+        Mm[k] -= h
+        vp, _ = oracle.warp(img, Mp, dims, fill=FILL, exact=True, photo=ph)
+        vm, _ = oracle.warp(img, Mm, dims, fill=FILL, exact=True, photo=ph)
+        fd = (np.vdot(vp, g) - np.vdot(vm, g)) / (2 * h)
+        assert g_M[k] == pytest.approx(fd, rel=1e-5, abs=1e-5 * np.abs(g_M).max())
+    with pytest.raises(Exception):
+        oracle.photometric_adjoint(g, PhotoParams(window=True))
+
+
 def test_displacement_gradient_finite_differences():
     rng = np.random.default_rng(14)
     dims = (12, 12, 12)
