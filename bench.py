@@ -14,7 +14,8 @@ parameter draws.
 
 Also reported in the same JSON line: the kernel-only roofline of the fused
 batched kernel (timed over the same input sets and parameter draws as the
-steps) against the VALU issue peak, with its fraction of HBM bandwidth
+steps): algorithmic bytes per launch over its duration against the 8 TB/s
+HBM peak, with the rocprofv3-measured traffic and the VALU issue fraction
 beside it; the CPU oracle timed on this host; and secondary workloads
 (full-resolution 512x512x320 volume; forward and forward+backward of the
 differentiable warp on 8 x 128^3; the nonrigid B-spline warp on 4 x 256^3;
@@ -37,10 +38,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 C3_OUT = (120, 120, 160)
-# Launch shape of the batched kernel (tile, workgroups per CU, LDS cells,
-# LDS cell format), the fastest in sweeps over tile shapes and LDS
-# reservations on this workload; --autotune re-runs the sweep.
-C3_TUNING = ((16, 16, 16), 0, 8176, 0)
+# The batch plans take their launch shape (tile, workgroups per CU, LDS cells,
+# LDS cell format) from the library's autotune cache, loaded from this file;
+# `--autotune` re-runs the sweep on this workload and rewrites the file.
+TUNING_CACHE = os.path.join(ROOT, "paper_1811_11226_amd", "autotune_cache.txt")
+C3_CANDIDATES = [(tile, 0, lds, fmt) for tile in [(8, 16, 16), (16, 16, 16), (16, 16, 32)]
+                 for lds in (0, 6128, 8176, 12272) for fmt in (0, 1)]
 
 # VALU roofline.  Peak: 256 CUs x 64 lanes x 2.4 GHz non-packed lane-ops
 # (one FP32/INT32 op per lane per cycle; transcendentals and 32x32->64-bit
@@ -148,7 +151,7 @@ class C3Set:
     """One 16-volume input batch resident in HBM with its outputs, a batch
     plan, and a pool of parameter draws."""
 
-    def __init__(self, batch, n_pool, dev, tuning=C3_TUNING):
+    def __init__(self, batch, n_pool, dev):
         import numpy as np
         import torch
 
@@ -180,8 +183,7 @@ class C3Set:
                                  fill=j.fill, label_fill=j.label_fill, photo=ph)
                   for k, (j, (M, ph)) in enumerate(zip(self.jobs, entry))]
             self.job_arrays.append(cj)
-        self.plan = ctaug.BatchPlan(self.job_arrays[0], tile=tuning[0], wg_per_cu=tuning[1],
-                                    lds_cells=tuning[2], lds_format=tuning[3])
+        self.plan = ctaug.BatchPlan(self.job_arrays[0])      # launch shape from the cache
 
     def voxels(self):
         return len(self.jobs) * C3_OUT[0] * C3_OUT[1] * C3_OUT[2]
@@ -193,38 +195,46 @@ def run_c3(args, dev):
 
     import paper_1811_11226_amd as ctaug
     n_sets, n_pool = 3, 4
+    if os.path.exists(TUNING_CACHE) and not args.autotune:
+        n = ctaug.autotune_cache_load(TUNING_CACHE)
+        log(f"c3: autotune cache {os.path.relpath(TUNING_CACHE, ROOT)} ({n} entries)")
     log("c3: generating 3 x 16 phantoms")
     t0 = time.time()
     sets = [C3Set(b, n_pool, dev) for b in range(n_sets)]
     log(f"c3: inputs resident ({time.time() - t0:.1f} s)")
     stream = torch.cuda.Stream()
 
-    best, times = C3_TUNING, None
+    times = None
+    cached = ctaug.autotune_cache_lookup(sets[0].job_arrays[0]) is not None
     if args.autotune:
-        # sweep launch shapes on batch 0, then give every plan the winner
-        cands = [(tile, 0, lds, fmt) for tile in [(8, 16, 16), (16, 16, 16), (16, 16, 32)]
-                 for lds in (0, 6128, 8176, 12272) for fmt in (0, 1)]
+        # sweep launch shapes on batch 0 (the winner enters the library's
+        # cache), save the cache, and rebuild every plan from it
         with torch.cuda.stream(stream):
-            best, times = sets[0].plan.autotune(cands, reps=3)
-        order = sorted(range(len(cands)), key=lambda i: times[i])
+            best, times = sets[0].plan.autotune(C3_CANDIDATES, reps=3)
+        order = sorted(range(len(C3_CANDIDATES)), key=lambda i: times[i])
         log(f"c3: autotune best {best} ({min(times):.3f} ms); top 5 "
-            f"{[(cands[i], round(times[i], 3)) for i in order[:5]]}")
-    for s in sets:
-        s.plan.close()
-        s.plan = ctaug.BatchPlan(s.job_arrays[0], tile=best[0], wg_per_cu=best[1],
-                                 lds_cells=best[2], lds_format=best[3])
+            f"{[(C3_CANDIDATES[i], round(times[i], 3)) for i in order[:5]]}")
+        ctaug.autotune_cache_save(TUNING_CACHE)
+        cached = True
+        for s in sets:
+            s.plan.close()
+            s.plan = ctaug.BatchPlan(s.job_arrays[0])
+    best = sets[0].plan.tuning()
+    log(f"c3: launch shape {best} ({'autotune cache' if cached else 'library default'})")
     with torch.cuda.stream(stream):
         for s in sets:
             s.plan.launch()
             s.plan.capture()
     torch.cuda.synchronize()
 
-    # descriptor arrays built once per parameter draw; each step uploads one
-    arrays = [[ctaug.BatchPlan.job_array(cj) for cj in s.job_arrays] for s in sets]
+    # descriptors validated and built once per (input set, parameter draw);
+    # a step installs one prepared set (one copy into pinned staging) and
+    # replays the graph (descriptor upload + launch)
+    prepared = [[s.plan.prepare(cj) for cj in s.job_arrays] for s in sets]
 
     def step(i):
         s = sets[i % n_sets]
-        s.plan.update(arrays[i % n_sets][(i // n_sets) % n_pool])
+        s.plan.update_prepared(prepared[i % n_sets][(i // n_sets) % n_pool])
         s.plan.replay()
 
     with torch.cuda.stream(stream):
@@ -241,8 +251,20 @@ def run_c3(args, dev):
         end.record(stream)
     torch.cuda.synchronize()
     step_ms = start.elapsed_time(end) / args.steps
+    # host cost of a step without the wait for the plan's previous replay: the
+    # same calls with the GPU idle before each
+    nowait = []
+    with torch.cuda.stream(stream):
+        for i in range(min(args.steps, 30)):
+            torch.cuda.synchronize()
+            h0 = time.perf_counter()
+            step(i)
+            nowait.append((time.perf_counter() - h0) * 1e3)
+    torch.cuda.synchronize()
+    host_nowait_ms = float(np.median(nowait))
     log(f"c3: {step_ms:.4f} ms per step (graph replay incl. descriptor upload); host enqueue "
-        f"{host_ms:.4f} ms per step")
+        f"{host_ms:.4f} ms per step in the timed loop, {host_nowait_ms:.4f} ms with nothing "
+        f"to wait for")
 
     # kernel-only duration of the fused batched kernel, per launch, same stream,
     # over the same (input set, parameter draw) sequence as the steps: one plan
@@ -251,9 +273,8 @@ def run_c3(args, dev):
     kplans = {}
     with torch.cuda.stream(stream):
         for (si, d) in sorted(set(pairs)):
-            kplans[(si, d)] = ctaug.BatchPlan(sets[si].job_arrays[d], tile=best[0],
-                                              wg_per_cu=best[1], lds_cells=best[2],
-                                              lds_format=best[3])
+            kplans[(si, d)] = ctaug.BatchPlan(sets[si].job_arrays[d])
+            assert kplans[(si, d)].tuning() == best
             kplans[(si, d)].launch()
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -283,6 +304,9 @@ def run_c3(args, dev):
             raise SystemExit("bench: batched output differs from the single-volume call")
     for kp in kplans.values():
         kp.close()
+    for row in prepared:
+        for pj in row:
+            pj.close()
 
     # algorithmic bytes and lane-ops of the timed kernel-only launches, averaged
     # over the same sequence of (set, draw) pairs
@@ -305,7 +329,8 @@ def run_c3(args, dev):
         f"(mean touched fraction f = {np.mean(touched):.3f}; {time.time() - t0:.1f} s)")
     log(f"c3: algorithmic lane-ops per launch {alg_ops / 1e9:.3f} G")
     return dict(sets=sets, step_ms=step_ms, kern_ms=kern_ms, kern_pct=kern_pct,
-                alg_bytes=alg_bytes, alg_ops=alg_ops,
+                alg_bytes=alg_bytes, alg_ops=alg_ops, host_ms=host_ms,
+                host_nowait_ms=host_nowait_ms, cached=cached,
                 tuning=best, tune_ms=times, voxels=sets[0].voxels(), stream=stream)
 
 
@@ -505,7 +530,7 @@ def run_c5(dev, stream, reps):
             "dense_field_fwd_ms": round(fd_ms, 4), "dense_field_fwd_bwd_ms": round(fbd_ms, 4)}
 
 
-def run_warp_only(sets, dev, stream, reps=30):
+def run_warp_only(sets, dev, stream, tuning, reps=30):
     """The 16-volume batches with the photometric chain and the labels off: the
     pure trilinear gather, whose bound is HBM (algorithmic bytes: 4 per output
     voxel written, 2 per touched int16 input voxel read).  The three input sets
@@ -519,8 +544,8 @@ def run_warp_only(sets, dev, stream, reps=30):
     for cs in sets:
         jobs = [ctaug.make_job(cs.imgs[k], cs.pool[0][k][0], cs.outs[k], fill=j.fill)
                 for k, j in enumerate(cs.jobs)]
-        plans.append(ctaug.BatchPlan(jobs, tile=C3_TUNING[0], wg_per_cu=C3_TUNING[1],
-                                     lds_cells=C3_TUNING[2], lds_format=C3_TUNING[3]))
+        plans.append(ctaug.BatchPlan(jobs, tile=tuning[0], wg_per_cu=tuning[1],
+                                     lds_cells=tuning[2], lds_format=tuning[3]))
         b = 0
         for k, j in enumerate(cs.jobs):
             ti, _, _ = touched_counts(j.in_dim, C3_OUT, cs.pool[0][k][0], dev)
@@ -716,7 +741,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: headline workload + copy reference only")
     ap.add_argument("--autotune", action="store_true",
-                    help="sweep launch shapes instead of the fixed C3_TUNING")
+                    help="sweep launch shapes on the headline workload and rewrite the "
+                         "autotune cache file the plans read")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/warp_batch_c3_traffic.txt from two rocprofv3 --pmc "
                          "counter_collection.csv files and exit (no GPU needed)")
@@ -768,32 +794,40 @@ def main():
                         "each with its own affine (rot U(+-30 deg), scale U(0.8,1.2), shift "
                         "U(+-10), crop) and photometrics (gain, offset, noise sigma 10 HU, "
                         "window [-1000,1000], gamma) -> 120x120x160 f32 + int8 NN labels; one "
-                        "persistent launch per batch replayed via hipGraph",
+                        + ("launch per batch with one workgroup per output tile"
+                           if r["tuning"][1] == 0 else
+                           f"persistent launch per batch ({r['tuning'][1]} workgroups per CU)")
+                        + ", descriptor upload and launch replayed from a hipGraph",
             "global_batch": 16,
             "out_dim": list(C3_OUT),
             "tile": list(r["tuning"][0]),
             "wg_per_cu": r["tuning"][1],
             "lds_cells": r["tuning"][2],
             "lds_format": "int16" if r["tuning"][3] == 1 else "f32",
+            "launch_shape_from": "autotune cache" if r["cached"] else "library default",
             "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(ALU_PEAK_TOPS, 2),
-            "unit": "TOP/s",
-            "frac": round(achieved / ALU_PEAK_TOPS, 4),
+            "bound": "hbm",
+            "achieved": round(hbm_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else int(traffic),
             "kernel": "k_warp_batch",
             "kernel_ms": round(r["kern_ms"], 5),
-            "algorithmic_ops_per_launch": int(r["alg_ops"]),
             "algorithmic_bytes_per_launch": int(r["alg_bytes"]),
-            "hbm_achieved_GBs": round(hbm_gbs, 1),
-            "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+            "traffic_over_algorithmic": None if traffic is None else
+            round(traffic / r["alg_bytes"], 3),
             "copy_kernel_GBs": round(copy_gbs, 1),
-            "hbm_frac_of_copy": round(hbm_gbs / copy_gbs, 4),
+            "frac_of_copy": round(hbm_gbs / copy_gbs, 4),
             "kernel_ms_p10_p50_p90": [round(v, 5) for v in r["kern_pct"]],
+            "valu": {"achieved_TOPs": round(achieved, 3), "peak_TOPs": round(ALU_PEAK_TOPS, 2),
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                     "algorithmic_lane_ops_per_launch": int(r["alg_ops"])},
         },
+        "host_enqueue_ms_per_step": {"timed_loop": round(r["host_ms"], 4),
+                                     "without_wait": round(r["host_nowait_ms"], 4)},
         "device": {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
                    "cus": props.multi_processor_count, "hip": torch.version.hip},
     }
@@ -809,7 +843,7 @@ def main():
         log("secondary: 4 x 256^3 nonrigid fwd / fwd+bwd")
         sec["nonrigid_4x256"] = run_c5(dev, stream, reps=5)
         log("secondary: warp only")
-        sec["warp_only_c3"] = run_warp_only(r["sets"], dev, stream)
+        sec["warp_only_c3"] = run_warp_only(r["sets"], dev, stream, r["tuning"])
         log("secondary: host-to-device FIFO")
         sec["host_fifo_c3"] = run_fifo(r["sets"][0], dev)
         result["secondary"] = sec

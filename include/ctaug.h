@@ -400,8 +400,10 @@ typedef struct ctaug_batch_plan ctaug_batch_plan;
 
 /* Create a plan for n_jobs jobs whose shapes are those of jobs[] (host
  * array).  Allocates the device job table and pinned staging (freed by
- * ctaug_batch_plan_destroy).  tune == NULL picks the default launch shape.
- * Errors: EINVAL, EDTYPE, ESHAPE, EHIP. */
+ * ctaug_batch_plan_destroy).  tune == NULL takes the autotune cache's entry
+ * for this device and batch class (see ctaug_autotune_cache_lookup), else the
+ * default launch shape (8 x 16 x 16 tiles, one workgroup per tile, LDS sized
+ * from the jobs, FP32 cells).  Errors: EINVAL, EDTYPE, ESHAPE, EHIP. */
 ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n_jobs,
                                      const ctaug_tuning *tune, ctaug_batch_plan **plan);
 
@@ -412,6 +414,24 @@ ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n_jobs,
  * on the GPU (its upload reads the staging buffer, its kernel the table)
  * before overwriting staging. */
 ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *plan, const ctaug_job *jobs);
+
+/* Updates prepared ahead of time: ctaug_batch_plan_prepare validates jobs
+ * against the plan and builds their descriptors once (host memory owned by
+ * *out, no device work); ctaug_batch_plan_update_prepared then installs them
+ * exactly as ctaug_batch_plan_update would (same wait for the plan's last
+ * launch, run or replay), with no per-call validation: one copy into the
+ * pinned staging buffer.  A prepared set belongs to its plan and to the
+ * plan's current launch shape: after ctaug_batch_plan_autotune it is stale
+ * and update_prepared returns EINVAL (prepare again).  The caller keeps the
+ * jobs' buffers alive and unchanged in shape while a prepared set may be
+ * installed.  Errors: as ctaug_batch_plan_update; EINVAL for another plan's
+ * or a stale set. */
+typedef struct ctaug_batch_jobs ctaug_batch_jobs;
+ctaug_status ctaug_batch_plan_prepare(ctaug_batch_plan *plan, const ctaug_job *jobs,
+                                      ctaug_batch_jobs **out);
+ctaug_status ctaug_batch_plan_update_prepared(ctaug_batch_plan *plan,
+                                              const ctaug_batch_jobs *jobs);
+ctaug_status ctaug_batch_jobs_destroy(ctaug_batch_jobs *jobs);
 
 /* Enqueue: upload the job table (async copy from pinned staging) and run one
  * persistent launch that warps every job.  Results equal ctaug_warp_affine
@@ -432,7 +452,8 @@ ctaug_status ctaug_batch_plan_capture(ctaug_batch_plan *plan, void *stream);
 ctaug_status ctaug_batch_plan_replay(ctaug_batch_plan *plan, void *stream);
 
 /* Time each candidate launch shape on the plan's current jobs (HIP events,
- * `reps` launches each, after one warm-up) and keep the fastest in the plan.
+ * `reps` launches each, after one warm-up) and keep the fastest in the plan
+ * and in the autotune cache (under this device and the plan's batch class).
  * The jobs' outputs are overwritten (with identical results).  Synchronises
  * `stream`.  best (host, may be NULL) receives the choice; times_ms (host
  * float[n_cand], may be NULL) the mean time per launch of each candidate. */
@@ -442,6 +463,27 @@ ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *plan, const ctaug_tunin
 
 ctaug_status ctaug_batch_plan_get_tuning(const ctaug_batch_plan *plan, ctaug_tuning *out);
 ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *plan);
+
+/* Autotune cache: the library's only state beyond plans and pipelines (one per
+ * process, thread-safe).  An entry maps (device architecture name and compute
+ * unit count; batch class) to the launch shape ctaug_batch_plan_autotune
+ * chose.  The batch class is: the inputs' dtype specialisation (all int16,
+ * all FP32, mixed; B-spline jobs apart), ceil(log2(n_jobs)),
+ * ceil(log2(largest output voxel count)), and whether any job warps labels or
+ * draws noise.
+ *
+ * lookup: *found = 1 and *out = the entry for these jobs on the current
+ * device, else *found = 0 (jobs validated as by ctaug_batch_plan_create;
+ * ENODEV without a device).  save: write every entry as text to path (a
+ * header line, then one line per entry).  load: read such a file and merge
+ * its entries (replacing equal keys); *n_entries (may be NULL) receives the
+ * count; a malformed file (bad header, field count or launch shape) merges
+ * nothing and returns EINVAL.  clear: drop every entry.  Host only. */
+ctaug_status ctaug_autotune_cache_lookup(const ctaug_job *jobs, int32_t n_jobs, ctaug_tuning *out,
+                                         int32_t *found);
+ctaug_status ctaug_autotune_cache_save(const char *path);
+ctaug_status ctaug_autotune_cache_load(const char *path, int32_t *n_entries);
+ctaug_status ctaug_autotune_cache_clear(void);
 
 /* ------------------------------------------------------------------------ */
 /* Host-to-device FIFO (Sec. "GPU-accelerated data augmentation": volumes    */

@@ -90,6 +90,14 @@ SIGNATURES = {
     "ctaug_bspline_upsample": (_S, [_P, _PI64, _PI64, _P, _P]),
     "ctaug_bspline_adjoint_workspace": (ctypes.c_size_t, [_PI64, _PI64]),
     "ctaug_bspline_upsample_adjoint": (_S, [_P, _PI64, _PI64, _P, _P, ctypes.c_size_t, _P]),
+    "ctaug_batch_plan_prepare": (_S, [_P, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_void_p)]),
+    "ctaug_batch_plan_update_prepared": (_S, [_P, _P]),
+    "ctaug_batch_jobs_destroy": (_S, [_P]),
+    "ctaug_autotune_cache_lookup": (_S, [ctypes.POINTER(Job), ctypes.c_int32,
+                                         ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_int32)]),
+    "ctaug_autotune_cache_save": (_S, [ctypes.c_char_p]),
+    "ctaug_autotune_cache_load": (_S, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
+    "ctaug_autotune_cache_clear": (_S, []),
     "ctaug_pipeline_create": (_S, [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
     "ctaug_pipeline_acquire": (_S, [_P, ctypes.POINTER(ctypes.c_void_p)]),
     "ctaug_pipeline_submit": (_S, [_P, _PV, _PV, _PF, ctypes.c_float, ctypes.c_int32,

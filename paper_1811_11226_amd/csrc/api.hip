@@ -3,8 +3,11 @@
 // (device job table + pinned staging + HIP graph + autotuner).
 #include <cmath>
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "ctaug.h"
@@ -823,6 +826,8 @@ struct ctaug_batch_plan {
     hipEvent_t upload_done = nullptr;
     bool upload_recorded = false;
     hipGraphExec_t exec = nullptr;
+    std::string arch;                   // device architecture name (autotune cache key)
+    uint64_t generation = 0;            // bumped by every (re)tiling
 };
 
 namespace {
@@ -938,6 +943,7 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     }
     p->lds_cells = cells;
     p->total = (int32_t)total;
+    ++p->generation;                    // descriptors prepared for the old tiling are stale
     const int64_t tiles8 = ((total + 7) / 8) * 8;
     int64_t grid = t.wg_per_cu > 0 ? (int64_t)p->num_cu * t.wg_per_cu : tiles8;
     grid = std::max<int64_t>(8, (grid / 8) * 8);
@@ -966,6 +972,190 @@ ctaug_status enqueue(ctaug_batch_plan *p, hipStream_t s)
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Autotune cache: the launch shape ctaug_batch_plan_autotune chose, keyed by
+// the device (architecture name, compute units) and a class of batch shapes
+// (input dtype specialisation, job count and largest output rounded to powers
+// of two, labels / noise present).  ctaug_batch_plan_create consults it when
+// given no tuning; save / load persist it as text.  The only mutable state of
+// the library besides plans and pipelines; guarded by a mutex.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct TuneKey {
+    std::string arch;
+    int32_t cus, mode, njobs_log, vox_log, flags;
+    bool operator==(const TuneKey &o) const
+    {
+        return arch == o.arch && cus == o.cus && mode == o.mode && njobs_log == o.njobs_log &&
+               vox_log == o.vox_log && flags == o.flags;
+    }
+};
+
+std::mutex g_cache_mu;
+std::vector<std::pair<TuneKey, ctaug_tuning>> g_cache;
+
+int ceil_log2(int64_t v)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < v)
+        ++l;
+    return l;
+}
+
+// Key of a batch: mode 0 mixed, 1 all int16, 3 all FP32 (the launch's dtype
+// specialisations), +8 for B-spline jobs.
+TuneKey tune_key(const std::string &arch, int cus, const std::vector<FwdJob> &jobs, bool spline)
+{
+    bool all_i16 = true, all_f32 = true, labels = false, noise = false;
+    int64_t vox = 1;
+    for (const FwdJob &J : jobs) {
+        all_i16 = all_i16 && J.dtype == kI16;
+        all_f32 = all_f32 && J.dtype == kF32;
+        labels = labels || (J.flags & kFlagLabels);
+        noise = noise || (J.flags & kFlagNoise);
+        vox = std::max<int64_t>(vox, (int64_t)J.ox * J.oy * J.oz);
+    }
+    TuneKey k;
+    k.arch = arch;
+    k.cus = cus;
+    k.mode = (all_i16 ? 1 : all_f32 ? 3 : 0) + (spline ? 8 : 0);
+    k.njobs_log = ceil_log2((int64_t)jobs.size());
+    k.vox_log = ceil_log2(vox);
+    k.flags = (labels ? 1 : 0) | (noise ? 2 : 0);
+    return k;
+}
+
+bool cache_find(const TuneKey &k, ctaug_tuning &out)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (const auto &e : g_cache)
+        if (e.first == k) {
+            out = e.second;
+            return true;
+        }
+    return false;
+}
+
+void cache_put(const TuneKey &k, const ctaug_tuning &t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (auto &e : g_cache)
+        if (e.first == k) {
+            e.second = t;
+            return;
+        }
+    g_cache.emplace_back(k, t);
+}
+
+bool device_id(std::string &arch, int &cus)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return false;
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos)
+        arch.resize(colon);            // gfx950, without target features
+    cus = prop.multiProcessorCount;
+    return true;
+}
+
+constexpr const char *kCacheHeader = "# ctaug autotune cache v1";
+
+}  // namespace
+
+extern "C" ctaug_status ctaug_autotune_cache_save(const char *path)
+{
+    if (!path)
+        return CTAUG_EINVAL;
+    std::vector<std::pair<TuneKey, ctaug_tuning>> snap;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        snap = g_cache;
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f)
+        return CTAUG_EINVAL;
+    bool ok = std::fprintf(f, "%s\n", kCacheHeader) > 0;
+    for (const auto &e : snap) {
+        const TuneKey &k = e.first;
+        const ctaug_tuning &t = e.second;
+        ok = ok && std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.cus,
+                                k.mode, k.njobs_log, k.vox_log, k.flags, t.tile[0], t.tile[1],
+                                t.tile[2], t.wg_per_cu, t.lds_cells, t.lds_format) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? CTAUG_OK : CTAUG_EINVAL;
+}
+
+extern "C" ctaug_status ctaug_autotune_cache_load(const char *path, int32_t *n_entries)
+{
+    if (!path)
+        return CTAUG_EINVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return CTAUG_EINVAL;
+    std::vector<std::pair<TuneKey, ctaug_tuning>> read;
+    char line[512];
+    bool ok = std::fgets(line, sizeof line, f) != nullptr &&
+              std::strncmp(line, kCacheHeader, std::strlen(kCacheHeader)) == 0;
+    while (ok && std::fgets(line, sizeof line, f)) {
+        if (line[0] == '\n' || line[0] == '#')
+            continue;
+        char arch[64];
+        TuneKey k;
+        ctaug_tuning t;
+        const int got = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d", arch, &k.cus,
+                                    &k.mode, &k.njobs_log, &k.vox_log, &k.flags, &t.tile[0],
+                                    &t.tile[1], &t.tile[2], &t.wg_per_cu, &t.lds_cells,
+                                    &t.lds_format);
+        Tiling TL;
+        ok = got == 12 && tiling_of(&t, TL) == CTAUG_OK && k.cus > 0;
+        k.arch = arch;
+        if (ok)
+            read.emplace_back(k, t);
+    }
+    std::fclose(f);
+    if (!ok)
+        return CTAUG_EINVAL;           // nothing merged from a malformed file
+    for (const auto &e : read)
+        cache_put(e.first, e.second);
+    if (n_entries)
+        *n_entries = (int32_t)read.size();
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_autotune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_cache.clear();
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_autotune_cache_lookup(const ctaug_job *jobs, int32_t n_jobs,
+                                                    ctaug_tuning *out, int32_t *found)
+{
+    if (!jobs || !out || !found || n_jobs <= 0 || n_jobs > (1 << 20))
+        return CTAUG_EINVAL;
+    std::vector<FwdJob> js(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        if ((jobs[i].ctrl != nullptr) != (jobs[0].ctrl != nullptr))
+            return CTAUG_EINVAL;
+        const ctaug_status st = job_from_public(jobs[i], kDefaultTiling, js[i]);
+        if (st != CTAUG_OK)
+            return st;
+    }
+    std::string arch;
+    int cus = 0;
+    if (!device_id(arch, cus))
+        return CTAUG_ENODEV;
+    *found = cache_find(tune_key(arch, cus, js, jobs[0].ctrl != nullptr), *out) ? 1 : 0;
+    return CTAUG_OK;
+}
 
 extern "C" ctaug_status ctaug_batch_plan_destroy(ctaug_batch_plan *p)
 {
@@ -1027,6 +1217,9 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
         return CTAUG_ENODEV;
     }
     p->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    p->arch = prop.gcnArchName;
+    if (p->arch.find(':') != std::string::npos)
+        p->arch.resize(p->arch.find(':'));
     if (hipHostMalloc(reinterpret_cast<void **>(&p->staging), sizeof(FwdJob) * n_jobs,
                       hipHostMallocDefault) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&p->table), sizeof(FwdJob) * n_jobs) != hipSuccess ||
@@ -1036,7 +1229,13 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
         ctaug_batch_plan_destroy(p);
         return CTAUG_EHIP;
     }
-    ctaug_tuning t = tune ? *tune : ctaug_tuning{{8, 16, 16}, 0, 0, 0};
+    // no tuning given: the cached autotune result for this device and batch
+    // class, else the default shape
+    ctaug_tuning t = ctaug_tuning{{8, 16, 16}, 0, 0, 0};
+    if (tune)
+        t = *tune;
+    else
+        (void)cache_find(tune_key(p->arch, p->num_cu, p->jobs, p->spline), t);
     st = apply_tiling(p, t);
     if (st != CTAUG_OK) {
         ctaug_batch_plan_destroy(p);
@@ -1046,11 +1245,14 @@ extern "C" ctaug_status ctaug_batch_plan_create(const ctaug_job *jobs, int32_t n
     return CTAUG_OK;
 }
 
-extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug_job *jobs)
+namespace {
+
+// Validate jobs against plan p and build their descriptors for its current
+// tiling (sub-tile shapes included): no device work, no waiting.
+ctaug_status prepare_jobs(const ctaug_batch_plan *p, const ctaug_job *jobs,
+                          std::vector<FwdJob> &next)
 {
-    if (!p || !jobs)
-        return CTAUG_EINVAL;
-    std::vector<FwdJob> next(p->n);
+    next.resize(p->n);
     for (int i = 0; i < p->n; ++i) {
         if ((jobs[i].ctrl != nullptr) != p->spline)
             return CTAUG_EINVAL;           // the plan holds only affine or only B-spline jobs
@@ -1066,15 +1268,74 @@ extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug
             (p->all_f32 && next[i].dtype != CTAUG_F32))
             return CTAUG_EDTYPE;           // the launch was specialised for the creation dtypes
     }
-    if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
-        return CTAUG_EHIP;
     for (int i = 0; i < p->n; ++i) {
         if (p->elem_bytes == 2)
             next[i].flags |= kFlagLds16;
         set_subtiles(next[i], p->TL, p->lds_cells);
     }
+    return CTAUG_OK;
+}
+
+// Wait until the plan's last launch / run / replay no longer reads staging or
+// table, then install the descriptors.
+ctaug_status commit_jobs(ctaug_batch_plan *p, const std::vector<FwdJob> &next)
+{
+    if (p->upload_recorded && hipEventSynchronize(p->upload_done) != hipSuccess)
+        return CTAUG_EHIP;
     p->jobs = next;
     std::memcpy(p->staging, p->jobs.data(), sizeof(FwdJob) * p->n);
+    return CTAUG_OK;
+}
+
+}  // namespace
+
+struct ctaug_batch_jobs {
+    const ctaug_batch_plan *plan = nullptr;
+    uint64_t generation = 0;            // the plan's tiling generation at prepare time
+    std::vector<FwdJob> jobs;
+};
+
+extern "C" ctaug_status ctaug_batch_plan_update(ctaug_batch_plan *p, const ctaug_job *jobs)
+{
+    if (!p || !jobs)
+        return CTAUG_EINVAL;
+    std::vector<FwdJob> next;
+    const ctaug_status st = prepare_jobs(p, jobs, next);
+    return st != CTAUG_OK ? st : commit_jobs(p, next);
+}
+
+extern "C" ctaug_status ctaug_batch_plan_prepare(ctaug_batch_plan *p, const ctaug_job *jobs,
+                                                 ctaug_batch_jobs **out)
+{
+    if (!p || !jobs || !out)
+        return CTAUG_EINVAL;
+    ctaug_batch_jobs *b = new (std::nothrow) ctaug_batch_jobs();
+    if (!b)
+        return CTAUG_EINVAL;
+    const ctaug_status st = prepare_jobs(p, jobs, b->jobs);
+    if (st != CTAUG_OK) {
+        delete b;
+        return st;
+    }
+    b->plan = p;
+    b->generation = p->generation;
+    *out = b;
+    return CTAUG_OK;
+}
+
+extern "C" ctaug_status ctaug_batch_plan_update_prepared(ctaug_batch_plan *p,
+                                                         const ctaug_batch_jobs *b)
+{
+    if (!p || !b || b->plan != p || b->generation != p->generation)
+        return CTAUG_EINVAL;
+    return commit_jobs(p, b->jobs);
+}
+
+extern "C" ctaug_status ctaug_batch_jobs_destroy(ctaug_batch_jobs *b)
+{
+    if (!b)
+        return CTAUG_EINVAL;
+    delete b;
     return CTAUG_OK;
 }
 
@@ -1222,9 +1483,12 @@ extern "C" ctaug_status ctaug_batch_plan_autotune(ctaug_batch_plan *p, const cta
         return st;
     }
     st = apply_tiling(p, cand[best_i]);
-    if (st == CTAUG_OK && best)
+    if (st != CTAUG_OK)
+        return st;
+    cache_put(tune_key(p->arch, p->num_cu, p->jobs, p->spline), cand[best_i]);
+    if (best)
         *best = cand[best_i];
-    return st;
+    return CTAUG_OK;
 }
 
 // ---------------------------------------------------------------------------

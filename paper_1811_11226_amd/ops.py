@@ -377,6 +377,17 @@ class BatchPlan:
             raise ValueError(f"expected {self.n} jobs, got {len(arr)}")
         _lib.check(self._L.ctaug_batch_plan_update(self._h, arr), "ctaug_batch_plan_update")
 
+    def prepare(self, jobs):
+        """Descriptors of `jobs` validated and built once, for update_prepared()."""
+        arr = jobs if isinstance(jobs, ctypes.Array) else self.job_array(jobs)
+        if len(arr) != self.n:
+            raise ValueError(f"expected {self.n} jobs, got {len(arr)}")
+        return PreparedJobs(self, arr)
+
+    def update_prepared(self, prepared):
+        _lib.check(self._L.ctaug_batch_plan_update_prepared(self._h, prepared._h),
+                   "ctaug_batch_plan_update_prepared")
+
     def launch(self):
         _lib.check(self._L.ctaug_batch_plan_launch(self._h, _stream()), "ctaug_batch_plan_launch")
 
@@ -421,6 +432,59 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class PreparedJobs:
+    """A batch update prepared for one plan (ctaug_batch_plan_prepare)."""
+
+    def __init__(self, plan, arr):
+        self._L = plan._L
+        h = ctypes.c_void_p()
+        _lib.check(self._L.ctaug_batch_plan_prepare(plan._h, arr, ctypes.byref(h)),
+                   "ctaug_batch_plan_prepare")
+        self._h = h
+        self._arr = arr                 # the jobs' ctypes array stays alive with it
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ctaug_batch_jobs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# -- autotune cache ------------------------------------------------------------
+
+def autotune_cache_lookup(jobs):
+    """The cached launch shape (tile, wg_per_cu, lds_cells, lds_format) for a
+    batch of jobs on the current device, or None."""
+    arr = (_lib.Job * len(jobs))(*jobs)
+    t, found = _lib.Tuning(), ctypes.c_int32(0)
+    _lib.check(_lib.load().ctaug_autotune_cache_lookup(arr, len(jobs), ctypes.byref(t),
+                                                       ctypes.byref(found)),
+               "ctaug_autotune_cache_lookup")
+    return (tuple(t.tile), t.wg_per_cu, t.lds_cells, t.lds_format) if found.value else None
+
+
+def autotune_cache_save(path):
+    _lib.check(_lib.load().ctaug_autotune_cache_save(str(path).encode()),
+               "ctaug_autotune_cache_save")
+
+
+def autotune_cache_load(path):
+    """Merge a saved cache; returns the number of entries read."""
+    n = ctypes.c_int32(0)
+    _lib.check(_lib.load().ctaug_autotune_cache_load(str(path).encode(), ctypes.byref(n)),
+               "ctaug_autotune_cache_load")
+    return n.value
+
+
+def autotune_cache_clear():
+    _lib.check(_lib.load().ctaug_autotune_cache_clear(), "ctaug_autotune_cache_clear")
 
 
 # -- resampling pre-step ------------------------------------------------------

@@ -516,3 +516,45 @@ def test_smoothing_validation(L):
                                    None) == EINVAL                                   # R > 160
     need = L.ctaug_gaussian_smooth_workspace((ctypes.c_int64 * 3)(8, 8, 8))
     assert need == 8 * 8 * 8 * 4
+
+
+# -- autotune cache (host side) -------------------------------------------------
+
+def test_autotune_cache_save_load_round_trip(L, tmp_path):
+    """A saved cache loads back entry for entry; malformed files merge nothing."""
+    assert L.ctaug_autotune_cache_clear() == OK
+    good = tmp_path / "cache.txt"
+    good.write_text("# ctaug autotune cache v1\n"
+                    "gfx950 256 1 4 22 3 16 16 16 0 8176 0\n"
+                    "gfx950 256 3 3 21 0 8 16 16 2 0 1\n")
+    n = ctypes.c_int32(-1)
+    assert L.ctaug_autotune_cache_load(str(good).encode(), ctypes.byref(n)) == OK
+    assert n.value == 2
+    out = tmp_path / "out.txt"
+    assert L.ctaug_autotune_cache_save(str(out).encode()) == OK
+    lines = out.read_text().splitlines()
+    assert lines[0] == "# ctaug autotune cache v1"
+    assert sorted(lines[1:]) == sorted(good.read_text().splitlines()[1:])
+    # reloading replaces equal keys instead of duplicating them
+    assert L.ctaug_autotune_cache_load(str(out).encode(), None) == OK
+    assert L.ctaug_autotune_cache_save(str(out).encode()) == OK
+    assert len(out.read_text().splitlines()) == 3
+    for bad in ["no header\ngfx950 256 1 4 22 3 16 16 16 0 8176 0\n",
+                "# ctaug autotune cache v1\ngfx950 256 1 4 22 3 16 16\n",
+                "# ctaug autotune cache v1\ngfx950 256 1 4 22 3 16 16 12 0 8176 0\n",
+                "# ctaug autotune cache v1\ngfx950 256 1 4 22 3 16 16 16 0 8176 7\n"]:
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        assert L.ctaug_autotune_cache_load(str(f).encode(), None) == EINVAL
+    assert L.ctaug_autotune_cache_load(str(tmp_path / "missing.txt").encode(), None) == EINVAL
+    assert L.ctaug_autotune_cache_save(None) == EINVAL
+    assert L.ctaug_autotune_cache_clear() == OK
+    assert L.ctaug_autotune_cache_save(str(out).encode()) == OK
+    assert out.read_text().splitlines() == ["# ctaug autotune cache v1"]
+
+
+def test_prepared_update_validation(L):
+    h = ctypes.c_void_p()
+    assert L.ctaug_batch_plan_prepare(None, None, ctypes.byref(h)) == EINVAL
+    assert L.ctaug_batch_plan_update_prepared(None, None) == EINVAL
+    assert L.ctaug_batch_jobs_destroy(None) == EINVAL

@@ -978,6 +978,7 @@ def test_autotune_picks_a_candidate_and_results_hold():
                                      out_dim=j.out_dim)
         assert torch.equal(out, s_out)
     plan.close()
+    ctaug.autotune_cache_clear()
 
 
 def test_autotune_then_run_uses_the_winning_tables():
@@ -1001,6 +1002,7 @@ def test_autotune_then_run_uses_the_winning_tables():
                                           out_dim=j.out_dim)
         assert torch.equal(out, s_out) and torch.equal(lout, s_lout)
     plan.close()
+    ctaug.autotune_cache_clear()
 
 
 # ---------------------------------------------------------------------------
@@ -1099,3 +1101,77 @@ def test_affine_backward_nonfinite_gradients(scale):
     fin = np.isfinite(r_img)
     assert_grad(gi[fin], r_img[fin], "finite cells")
     assert np.isnan(_np(g_M)).all() and np.isnan(r_M).all()
+
+
+def test_autotune_cache_feeds_plans_created_without_tuning(tmp_path):
+    """The autotuner's choice is cached per device and batch class: a plan
+    created later without a tuning takes it, also after a save / clear / load
+    round trip; results stay bitwise those of single calls."""
+    ctaug.autotune_cache_clear()
+    T = _batch_jobs(n=3)
+    jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
+            for (j, M, img, lbl, out, lout) in T]
+    assert ctaug.autotune_cache_lookup(jobs) is None
+    plan = ctaug.BatchPlan(jobs)
+    assert plan.tuning()[0] == (8, 16, 16)                 # the default shape
+    cands = [((4, 8, 32), 0, 0, 0), ((16, 16, 16), 0, 6128, 1)]
+    best, _ = plan.autotune(cands, reps=2)
+    plan.close()
+    assert ctaug.autotune_cache_lookup(jobs) == best
+    path = tmp_path / "tune.txt"
+    ctaug.autotune_cache_save(path)
+    ctaug.autotune_cache_clear()
+    assert ctaug.autotune_cache_lookup(jobs) is None
+    assert ctaug.autotune_cache_load(path) == 1
+    plan2 = ctaug.BatchPlan(jobs)
+    assert plan2.tuning()[0] == best[0] and plan2.tuning()[3] == best[3]
+    plan2.launch()
+    for (j, M, img, lbl, out, lout) in T:
+        s_out, s_lout = ctaug.warp_affine(img, M, lbl=lbl, fill=j.fill, photo=j.photo,
+                                          out_dim=j.out_dim)
+        assert torch.equal(out, s_out) and torch.equal(lout, s_lout)
+    plan2.close()
+    ctaug.autotune_cache_clear()
+
+
+def test_prepared_updates_equal_updates_and_go_stale_on_retuning():
+    """Prepared descriptor sets installed by update_prepared give the outputs
+    of plain updates (graph replays); a set prepared before autotuning is
+    refused afterwards, and one prepared for another plan is refused."""
+    T = _batch_jobs(n=3)
+    rng = np.random.default_rng(41)
+    draws = []
+    for rep in range(3):
+        jobs, items = [], []
+        for (j, M, img, lbl, out, lout) in T:
+            prm = draw_affine_params(rng, AugmentRanges(), j.in_dim, j.out_dim)
+            _, M2 = ctaug.affine_matrix(prm, j.in_dim, j.out_dim)
+            ph = draw_photo(rng, AugmentRanges(), seed=2000 + rep, volume_id=j.volume_id)
+            jobs.append(ctaug.make_job(img, M2, out, lbl, lout, fill=j.fill, photo=ph))
+            items.append((j, M2, ph, img, lbl, out, lout))
+        draws.append((jobs, items))
+    plan = ctaug.BatchPlan(draws[0][0])
+    prepared = [plan.prepare(jobs) for jobs, _ in draws]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture()
+    for rep in (2, 0, 1):
+        plan.update_prepared(prepared[rep])
+        with torch.cuda.stream(stream):
+            plan.replay()
+        stream.synchronize()
+        for (j, M2, ph, img, lbl, out, lout) in draws[rep][1]:
+            s_out, s_lout = ctaug.warp_affine(img, M2, lbl=lbl, fill=j.fill, photo=ph,
+                                              out_dim=j.out_dim)
+            assert torch.equal(out, s_out) and torch.equal(lout, s_lout), f"draw {rep}"
+    other = ctaug.BatchPlan(draws[0][0])
+    with pytest.raises(ctaug._lib.CtaugError):
+        other.update_prepared(prepared[0])
+    other.close()
+    plan.autotune([((16, 16, 16), 0, 0, 0)], reps=1)
+    with pytest.raises(ctaug._lib.CtaugError):
+        plan.update_prepared(prepared[1])
+    for p in prepared:
+        p.close()
+    plan.close()
+    ctaug.autotune_cache_clear()
