@@ -256,6 +256,24 @@ ctaug_status ctaug_warp_affine_backward(const ctaug_vol *img_in, const float M[1
                                         ctaug_vol *grad_img, double *grad_M, void *ws,
                                         size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same adjoint
+ * as ctaug_warp_affine_backward, bit for bit in grad_M, without a workspace
+ * argument.  Its only scratch memory, the FP64 partial rows of grad_M (at
+ * most 2048 rows of 12 doubles), lives in a 192 KiB static device array of
+ * the library, one copy per GPU, held until the process ends.  The call
+ * allocates nothing (no hipMalloc / hipFree, no library allocation).  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams, or from
+ * several threads) race and must be serialised by the caller; each call
+ * overwrites every row it reads.  Errors: as ctaug_warp_affine_backward;
+ * EWORKSPACE if the output would need more partial rows than the array
+ * holds (no output shape does today). */
+ctaug_status ctaug_warp_affine_backward_noalloc(const ctaug_vol *img_in, const float M[12],
+                                                float fill, const ctaug_photo *photo,
+                                                const ctaug_vol *grad_out, ctaug_vol *grad_img,
+                                                double *grad_M, void *stream);
+
 /* Adjoint of ctaug_warp_displacement: as above (photo likewise), plus
  * grad_disp[i](p) = g(p) dV/dq_i(p) (device float SoA [3][Xo][Yo][Zo],
  * overwritten, or NULL). */

@@ -81,6 +81,8 @@ SIGNATURES = {
     "ctaug_warp_backward_workspace": (ctypes.c_size_t, [_PI64]),
     "ctaug_warp_affine_backward": (_S, [_PV, _PF, ctypes.c_float, ctypes.POINTER(Photo), _PV,
                                         _PV, _P, _P, ctypes.c_size_t, _P]),
+    "ctaug_warp_affine_backward_noalloc": (_S, [_PV, _PF, ctypes.c_float, ctypes.POINTER(Photo),
+                                                _PV, _PV, _P, _P]),
     "ctaug_warp_displacement_backward": (_S, [_PV, _PF, _P, ctypes.c_float, ctypes.POINTER(Photo),
                                               _PV, _PV, _P, _P, _P, ctypes.c_size_t, _P]),
     "ctaug_warp_bspline_backward_workspace": (ctypes.c_size_t, [_PI64, _PI64]),

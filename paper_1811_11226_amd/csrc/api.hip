@@ -525,11 +525,18 @@ static ctaug_status check_photo_adjoint(const ctaug_photo *photo)
     return photo && (photo->flags & CTAUG_PHOTO_WINDOW) ? CTAUG_EINVAL : CTAUG_OK;
 }
 
+namespace {
+ctaug_status scratch_address(void **out);
+constexpr size_t kScratchBytes = (size_t)kBwdMaxRows * 12 * sizeof(double);   // 192 KiB
+}  // namespace
+
+// use_scratch: the grad_M partials go to the library's static device array
+// (ws / ws_bytes ignored), looked up after every argument is validated.
 static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], const float *disp,
                                   bool need_disp, float fill, const ctaug_photo *photo,
                                   const ctaug_vol *grad_out,
                                   ctaug_vol *grad_img, double *grad_M, float *grad_disp, void *ws,
-                                  size_t ws_bytes, void *stream)
+                                  size_t ws_bytes, void *stream, bool use_scratch = false)
 {
     ctaug_status st;
     if ((st = check_vol(img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16, true)) != CTAUG_OK)
@@ -548,7 +555,9 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
         return st;
     if (grad_M) {
         const size_t need = ctaug_warp_backward_workspace(grad_out->dim);
-        if (need > 0 && (!ws || ws_bytes < need))
+        if (use_scratch && need > kScratchBytes)
+            return CTAUG_EWORKSPACE;   // more partial rows than the static array holds
+        if (!use_scratch && need > 0 && (!ws || ws_bytes < need))
             return CTAUG_EWORKSPACE;
     }
     FwdJob J;
@@ -561,6 +570,11 @@ static ctaug_status backward_impl(const ctaug_vol *img_in, const float M[12], co
     J.out = nullptr;
     if (empty(J) && !grad_M)
         return CTAUG_OK;
+    if (use_scratch) {
+        ws = nullptr;
+        if (grad_M && (st = scratch_address(&ws)) != CTAUG_OK)
+            return st;
+    }
     return hip_status(launch_warp_bwd(J, static_cast<const float *>(grad_out->data),
                                       grad_img ? static_cast<float *>(grad_img->data) : nullptr,
                                       need_disp ? grad_disp : nullptr, grad_M,
@@ -588,6 +602,54 @@ extern "C" ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in
 {
     return backward_impl(img_in, M, disp, true, fill, photo, grad_out, grad_img, grad_M,
                          grad_disp, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free adjoint: ctaug_warp_affine_backward with the grad_M partials
+// (the only scratch memory the affine adjoint uses) in a static device array
+// of the library instead of a caller workspace.  Each device holds its own
+// copy of the array at its own address, looked up once per device; host code
+// uses that address, never the array's name.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's copy of `scratch`.
+ctaug_status scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return CTAUG_EHIP;
+    if (dev < 0 || dev >= kMaxDevices)
+        return CTAUG_ENODEV;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return CTAUG_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CTAUG_OK;
+}
+
+}  // namespace
+
+extern "C" ctaug_status ctaug_warp_affine_backward_noalloc(const ctaug_vol *img_in,
+                                                           const float M[12], float fill,
+                                                           const ctaug_photo *photo,
+                                                           const ctaug_vol *grad_out,
+                                                           ctaug_vol *grad_img, double *grad_M,
+                                                           void *stream)
+{
+    return backward_impl(img_in, M, nullptr, false, fill, photo, grad_out, grad_img, grad_M,
+                         nullptr, nullptr, 0, stream, true);
 }
 
 // Workspace of ctaug_warp_bspline_backward: grad_M partials, then either the

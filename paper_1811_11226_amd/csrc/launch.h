@@ -39,6 +39,9 @@ hipError_t launch_noise(uint64_t v0, int64_t n, uint32_t vol, uint32_t k0, uint3
 hipError_t launch_box_muller(const uint32_t *words, int64_t npairs, float *out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
+// Rows of FP64 partials of grad_M the adjoint writes: one per persistent
+// workgroup, at most kBwdMaxRows.
+constexpr int64_t kBwdMaxRows = 2048;
 int64_t bwd_partial_rows(int64_t ox, int64_t oy, int64_t oz);
 // Adjoint of a warp.  A control grid (J.ctrl) requires bwd_spline_eval_ok(J.bs)
 // (every tile's z window of controls fits the kernel's row profiles); its

@@ -42,7 +42,7 @@ namespace ctaug {
 // adjoint accumulators of the same cells.
 constexpr Tiling kBwdTiling = {3, 3, 4};
 constexpr int32_t kBwdLdsCells = 12288;
-constexpr int64_t kBwdMaxGrid = 2048;
+constexpr int64_t kBwdMaxGrid = kBwdMaxRows;
 
 static int64_t bwd_tiles(int64_t ox, int64_t oy, int64_t oz)
 {
@@ -732,26 +732,31 @@ bool bwd_ctrl_fused(const BsplineGeom &B)
 // LDS (occupancy x compute units), cached per device, kernel and LDS size.
 static int resident_groups(const void *fn, size_t lds)
 {
+    // a fixed table (no heap allocation on the call path); when it is full
+    // the occupancy is queried again on every call
     struct Entry {
         int dev;
         const void *fn;
         size_t lds;
         int groups;
     };
+    constexpr int kEntries = 256;
     static std::mutex mu;
-    static std::vector<Entry> cache;
+    static Entry cache[kEntries];
+    static int used = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return 0;
     std::lock_guard<std::mutex> lock(mu);
-    for (const Entry &e : cache)
-        if (e.dev == dev && e.fn == fn && e.lds == lds)
-            return e.groups;
+    for (int i = 0; i < used; ++i)
+        if (cache[i].dev == dev && cache[i].fn == fn && cache[i].lds == lds)
+            return cache[i].groups;
     int cus = 0, occ = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, lds) != hipSuccess)
         return 0;
-    cache.push_back({dev, fn, lds, cus * occ});
+    if (used < kEntries)
+        cache[used++] = {dev, fn, lds, cus * occ};
     return cus * occ;
 }
 

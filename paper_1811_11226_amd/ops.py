@@ -235,6 +235,25 @@ def warp_affine_backward(img, M, grad_out, fill=-1000.0, want_img=True, want_M=T
     return _backward(img, M, grad_out, None, fill, want_img, want_M, False, photo)
 
 
+def warp_affine_backward_noalloc(img, M, grad_out, fill=-1000.0, photo=None, grad_img=None,
+                                 grad_M=None):
+    """ctaug_warp_affine_backward_noalloc: the affine adjoint with its scratch
+    in the library's static device array.  grad_img (float32, img's dims;
+    accumulated into) and grad_M (float64[12]; overwritten) are the caller's
+    tensors, either may be None."""
+    _require(img, "img", (torch.float32, torch.int16), strided=True)
+    _require(grad_out, "grad_out", (torch.float32,))
+    vi, vg = vol(img), vol(grad_out)
+    vgi = vol(grad_img) if grad_img is not None else None
+    ph = make_photo(photo)
+    p = ctypes.c_void_p(grad_M.data_ptr()) if grad_M is not None else None
+    st = _lib.load().ctaug_warp_affine_backward_noalloc(
+        ctypes.byref(vi), _M32(M), float(fill), _ref(ph), ctypes.byref(vg), _ref(vgi), p,
+        _stream())
+    _lib.check(st, "ctaug_warp_affine_backward_noalloc")
+    return grad_img, grad_M
+
+
 def warp_displacement_backward(img, M, disp, grad_out, fill=-1000.0, want_img=True,
                                want_M=True, want_disp=True, photo=None):
     """(grad_img, grad_M, grad_disp)."""

@@ -558,3 +558,21 @@ def test_prepared_update_validation(L):
     assert L.ctaug_batch_plan_prepare(None, None, ctypes.byref(h)) == EINVAL
     assert L.ctaug_batch_plan_update_prepared(None, None) == EINVAL
     assert L.ctaug_batch_jobs_destroy(None) == EINVAL
+
+
+def test_noalloc_backward_validation(L):
+    """The allocation-free adjoint validates like the workspace call before
+    touching the device."""
+    r = ctypes.byref
+    img, g = vol((8, 8, 8)), vol((64, 64, 64))
+    assert L.ctaug_warp_affine_backward_noalloc(None, mat(), 0.0, None, r(g), None, FAKE,
+                                                None) == EINVAL
+    assert L.ctaug_warp_affine_backward_noalloc(r(img), mat(), 0.0, None, None, None, FAKE,
+                                                None) == EINVAL
+    assert L.ctaug_warp_affine_backward_noalloc(r(img), mat(), 0.0, r(photo(flags=1)), r(g),
+                                                None, FAKE, None) == EINVAL
+    assert L.ctaug_warp_affine_backward_noalloc(r(img), mat(), 0.0, None, r(g),
+                                                r(vol((8, 8, 9))), None, None) == ESHAPE
+    assert L.ctaug_warp_affine_backward_noalloc(r(img), mat(), 0.0, None,
+                                                r(vol((0, 4, 4), data=None)), None, None,
+                                                None) == OK
