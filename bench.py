@@ -740,6 +740,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: headline workload + copy reference only")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="short run for rocprofv3: the 8 x 128^3 and 4 x 256^3 forward + "
+                         "adjoint workloads and the copy reference only")
     ap.add_argument("--autotune", action="store_true",
                     help="sweep launch shapes on the headline workload and rewrite the "
                          "autotune cache file the plans read")
@@ -767,6 +770,14 @@ def main():
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(0)
     log(f"device {props.name} {getattr(props, 'gcnArchName', '')} CUs={props.multi_processor_count}")
+
+    if args.profile_adjoint:
+        stream = torch.cuda.Stream()
+        copy_bandwidth(dev, stream, reps=3)
+        out = {"diff_affine_8x128": run_c4(dev, stream, reps=3),
+               "nonrigid_4x256": run_c5(dev, stream, reps=2)}
+        print(json.dumps(out), flush=True)
+        return
 
     r = run_c3(args, dev)
     stream = r["stream"]

@@ -90,6 +90,14 @@ __device__ __forceinline__ TileGeom box_geom(const FwdJob &J, int x0, int y0, in
     G.pitch = lds_pitch(G.e[2]);
     cells = G.e[0] * G.e[1] * G.pitch;
     G.cls = outside ? kOutside : (interior ? kInterior : kBoundary);
+    // an interior footprint whose last quad would reach past z = nz - 1 starts
+    // its z window earlier (the extra cells are in the volume), so that every
+    // staged quad of an interior tile lies inside the volume
+    if (G.cls == kInterior && 4 * G.quads <= J.nz && G.lo[2] + 4 * G.quads > J.nz) {
+        const int shift = G.lo[2] + 4 * G.quads - J.nz;
+        G.lo[2] -= shift;
+        G.e[2] += shift;
+    }
     // an int16 footprint must hold fill exactly
     G.lds = !outside && cells <= lds_cells && (!(J.flags & kFlagLds16) || (J.flags & kFlagFillInT));
     return G;
@@ -132,6 +140,38 @@ __device__ __forceinline__ void copy_quad(rsrc_t r, uint32_t off, float *dst, in
               (float)(int16_t)(w.y & 0xffffu), (float)((int32_t)w.y >> 16)};
 }
 
+// The raw bytes of four consecutive input cells of type T at element offset e
+// (one wide load), and their store as LDS cells of type LT.
+template <typename T> struct QuadRaw;
+template <> struct QuadRaw<float> {
+    typedef u32x4 type;
+    static __device__ __forceinline__ type load(rsrc_t r, uint32_t e)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, e * 4u, 0, 0);
+    }
+    static __device__ __forceinline__ void store(type w, float *dst)
+    {
+        *reinterpret_cast<u32x4 *>(dst) = w;
+    }
+};
+template <> struct QuadRaw<int16_t> {
+    typedef u32x2 type;
+    static __device__ __forceinline__ type load(rsrc_t r, uint32_t e)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, e * 2u, 0, 0);
+    }
+    static __device__ __forceinline__ void store(type w, int16_t *dst)
+    {
+        *reinterpret_cast<u32x2 *>(dst) = w;
+    }
+    static __device__ __forceinline__ void store(type w, float *dst)
+    {
+        *reinterpret_cast<f32x4 *>(dst) =
+            f32x4{(float)(int16_t)(w.x & 0xffffu), (float)((int32_t)w.x >> 16),
+                  (float)(int16_t)(w.y & 0xffffu), (float)((int32_t)w.y >> 16)};
+    }
+};
+
 // floor(a / b) for 0 <= a < 2^24, 0 < b < 2^16: FP32 reciprocal estimate and
 // one integer correction step.
 __device__ __forceinline__ int div_small(int a, int b, float rcp_b)
@@ -142,35 +182,35 @@ __device__ __forceinline__ int div_small(int a, int b, float rcp_b)
     return q;
 }
 
-// One quad of the footprint: input cells (gx, gy, gz0 .. gz0 + 3).  A quad
-// wholly inside the volume is copied with one wide load per array; a quad at
-// the volume's edge loads each cell from its index clamped into the volume
-// (every load stays in range) and substitutes fill / label_fill outside.
+// A quad of four input cells (gx, gy, gz0 .. gz0 + 3) wholly inside the volume,
+// at element offset e: one wide load per array.
 template <typename T, typename LT, bool LBL>
-__device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, int gx, int gy, int gz0,
-                                           LT *dst, int8_t *ldst)
+__device__ __forceinline__ void quad_inside(const Src &S, uint32_t e, LT *dst, int8_t *ldst)
+{
+    copy_quad(S.img, e * (uint32_t)sizeof(T), dst, T());
+    if (LBL)
+        *reinterpret_cast<uint32_t *>(ldst) = __builtin_amdgcn_raw_buffer_load_b32(S.lbl, e, 0, 0);
+}
+
+// A quad of an in-volume row (element offset e_row0 of its z = 0 cell) whose
+// z range leaves the volume: each cell is loaded from its z clamped into the
+// volume (every load stays in range) and replaced by fill / label_fill outside.
+template <typename T, typename LT, bool LBL>
+__device__ __forceinline__ void quad_partial(const FwdJob &J, const Src &S, int e_row0, int gz0,
+                                             LT *dst, int8_t *ldst)
 {
     constexpr uint32_t es = sizeof(T);
-    const bool row_in = (unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny;
-    if (row_in && gz0 >= 0 && gz0 + 3 < J.nz) {
-        const uint32_t e = elem_index(S, gx, gy, gz0);
-        copy_quad(S.img, e * es, dst, T());
-        if (LBL)
-            *reinterpret_cast<uint32_t *>(ldst) = __builtin_amdgcn_raw_buffer_load_b32(S.lbl, e, 0, 0);
-        return;
-    }
     const int8_t lfill = (int8_t)J.label_fill;
-    const uint32_t grow = elem_index(S, min(max(gx, 0), J.nx - 1), min(max(gy, 0), J.ny - 1), 0);
     const LT tfill = (LT)J.fill;
     LT v[4];
     uint32_t lp = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int gz = gz0 + u;
-        const uint32_t e = grow + (uint32_t)min(max(gz, 0), J.nz - 1);
+        const uint32_t e = (uint32_t)(e_row0 + min(max(gz, 0), J.nz - 1));
         const T raw = Elem<T>::raw(S.img, e * es, 0);
         const int8_t lab = LBL ? load_i8(S.lbl, e) : lfill;
-        const bool in = row_in && (unsigned)gz < (unsigned)J.nz;
+        const bool in = (unsigned)gz < (unsigned)J.nz;
         v[u] = in ? (LT)raw : tfill;
         if (LBL)
             lp |= (uint32_t)(uint8_t)(in ? lab : lfill) << (8 * u);
@@ -180,27 +220,131 @@ __device__ __forceinline__ void stage_quad(const FwdJob &J, const Src &S, int gx
         *reinterpret_cast<uint32_t *>(ldst) = lp;
 }
 
+// A quad of a row outside the volume: fill / label_fill, nothing loaded.
+template <typename LT, bool LBL>
+__device__ __forceinline__ void quad_fill(const FwdJob &J, LT *dst, int8_t *ldst)
+{
+    const LT tfill = (LT)J.fill;
+    const LT v[4] = {tfill, tfill, tfill, tfill};
+    store4(dst, v);
+    if (LBL)
+        *reinterpret_cast<uint32_t *>(ldst) = 0x01010101u * (uint32_t)(uint8_t)(int8_t)J.label_fill;
+}
+
+// Row walk of the footprint staging: the lane takes rows row, row + rpp, ...
+// (rpp = rows per pass), tracking the row's input cell (cx, cy), its element
+// offset and its LDS offset by additions of per-tile constants.
+struct RowWalk {
+    int row, cx, cy, e_row, l_row;     // e_row: element offset of cell (lo0 + cx, lo1 + cy, 0)
+    int rpp, step_x, step_y, ey, de, de_wrap, dl;
+
+    __device__ __forceinline__ void init(const Src &S, const TileGeom &G, int first_row,
+                                         int rows_per_pass, int lane_cell)
+    {
+        ey = G.e[1];
+        rpp = rows_per_pass;
+        const float rcp_y = 1.0f / (float)ey;
+        step_x = div_small(rpp, ey, rcp_y);            // rpp = step_x * ey + step_y
+        step_y = rpp - step_x * ey;
+        row = first_row;
+        cx = div_small(row, ey, rcp_y);
+        cy = row - cx * ey;
+        const int plane = S.ry * S.rsy;                 // elements per x plane
+        e_row = (G.lo[0] + cx) * plane + (G.lo[1] + cy) * S.rsy;
+        de = step_x * plane + step_y * S.rsy;
+        de_wrap = plane - ey * S.rsy;
+        l_row = row * G.pitch + lane_cell;
+        dl = rpp * G.pitch;
+    }
+    __device__ __forceinline__ void next()
+    {
+        row += rpp;
+        cx += step_x;
+        cy += step_y;
+        e_row += de;
+        l_row += dl;
+        if (cy >= ey) {
+            cy -= ey;
+            cx += 1;
+            e_row += de_wrap;
+        }
+    }
+};
+
 // Copy the tile's input footprint into LDS in the LDS cell type (labels as
 // int8), with fill / label_fill in cells outside the volume.  The footprint is
-// e[0] x e[1] rows of `quads` quads of 4 cells (row pitch G.pitch cells); the
-// workgroup's lanes take the quads in flat order, so every lane is busy
-// whatever the row length.
+// e[0] x e[1] rows of `quads` quads of 4 cells (row pitch G.pitch cells).
+// Each row is taken by LPR consecutive lanes (LPR the power of two >= quads,
+// at most 16; a lane takes quads q, q + LPR, ...), so a workgroup covers
+// 256 / LPR rows per pass; rows advance by additions (RowWalk), with no
+// per-quad division or multiplication.  An interior footprint (every quad
+// inside the volume, see box_geom) of at most 16 quads per row is copied
+// without any test: each lane issues the loads of four rows before it
+// converts and writes them.  Other footprints test each row and quad: rows
+// outside the volume are filled without loads, quads crossing its z ends
+// load per cell from clamped indices.
 template <typename T, typename LT, bool LBL>
 __device__ __forceinline__ void stage_quads(const FwdJob &J, const Src &S, const TileGeom &G,
                                             LT *s_img, int8_t *s_lbl)
 {
-    const int qpr = G.quads, ey = G.e[1];
-    const int nq = G.e[0] * ey * qpr;
-    const float rcp_q = 1.0f / (float)qpr, rcp_y = 1.0f / (float)ey;
-#pragma unroll 2
-    for (int f = threadIdx.x; f < nq; f += kThreads) {
-        const int row = div_small(f, qpr, rcp_q);
-        const int q = f - row * qpr;
-        const int cx = div_small(row, ey, rcp_y);
-        const int cy = row - cx * ey;
-        const int off = row * G.pitch + 4 * q;
-        stage_quad<T, LT, LBL>(J, S, G.lo[0] + cx, G.lo[1] + cy, G.lo[2] + 4 * q, s_img + off,
-                               s_lbl + off);
+    const int qpr = G.quads, rows = G.e[0] * G.e[1];
+    const int lpr_log = qpr > 8 ? 4 : qpr > 4 ? 3 : qpr > 2 ? 2 : qpr > 1 ? 1 : 0;
+    const int lpr = 1 << lpr_log;
+    const int ql = threadIdx.x & (lpr - 1);
+    RowWalk W;
+    W.init(S, G, threadIdx.x >> lpr_log, kThreads >> lpr_log, 4 * ql);
+    const bool fast = G.cls == kInterior && G.lo[2] >= 0 && G.lo[2] + 4 * qpr <= J.nz &&
+                      qpr <= 16;
+    if (fast) {
+        if (ql >= qpr)
+            return;                    // lanes beyond the row's quads stay idle
+        const int gz0 = G.lo[2] + 4 * ql;
+        constexpr int B = 4;           // rows whose loads are in flight together
+        for (; W.row < rows;) {
+            uint32_t e[B];
+            int l[B];
+            bool ok[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                ok[u] = W.row < rows;
+                e[u] = (uint32_t)(W.e_row + gz0);
+                l[u] = W.l_row;
+                W.next();
+            }
+            typename QuadRaw<T>::type w[B];
+            uint32_t lab[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const uint32_t eu = ok[u] ? e[u] : e[0];    // in the volume either way
+                w[u] = QuadRaw<T>::load(S.img, eu);
+                if (LBL)
+                    lab[u] = __builtin_amdgcn_raw_buffer_load_b32(S.lbl, eu, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                if (!ok[u])
+                    break;
+                QuadRaw<T>::store(w[u], s_img + l[u]);
+                if (LBL)
+                    *reinterpret_cast<uint32_t *>(s_lbl + l[u]) = lab[u];
+            }
+        }
+        return;
+    }
+    for (; W.row < rows; W.next()) {
+        const int gx = G.lo[0] + W.cx, gy = G.lo[1] + W.cy;
+        const bool row_in = (unsigned)gx < (unsigned)J.nx && (unsigned)gy < (unsigned)J.ny;
+        for (int q = ql; q < qpr; q += lpr) {
+            const int gz0 = G.lo[2] + 4 * q;
+            LT *dst = s_img + W.l_row + 4 * (q - ql);
+            int8_t *ldst = s_lbl + W.l_row + 4 * (q - ql);
+            if (!row_in)
+                quad_fill<LT, LBL>(J, dst, ldst);
+            else if (gz0 >= 0 && gz0 + 3 < J.nz)
+                quad_inside<T, LT, LBL>(S, (uint32_t)(W.e_row + gz0), dst, ldst);
+            else
+                quad_partial<T, LT, LBL>(J, S, W.e_row, gz0, dst, ldst);
+        }
     }
 }
 

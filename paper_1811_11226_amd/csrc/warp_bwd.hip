@@ -404,11 +404,10 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                     float K[8], tt[3];
                     if (lds) {
                         const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-                        const int bs = (int)mul24(mul24((uint32_t)((int)fx - G.lo[0]),
-                                                        (uint32_t)ey) +
-                                                      (uint32_t)((int)fy - G.lo[1]),
-                                                  (uint32_t)pitch) +
-                                       ((int)fz - G.lo[2]);
+                        // LDS cell (i - lo) . (sxy, pitch, 1) in exact FP32 (integers < 2^24)
+                        const int bs = (int)__builtin_fmaf(
+                            fx - (float)G.lo[0], (float)sxy,
+                            __builtin_fmaf(fy - (float)G.lo[1], (float)pitch, fz - (float)G.lo[2]));
                         tt[0] = qx - fx;
                         tt[1] = qy - fy;
                         tt[2] = qz - fz;

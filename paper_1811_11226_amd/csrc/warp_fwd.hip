@@ -50,7 +50,11 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
     Photo P = photo_of(J);
     const int runs_z_log = SL.lz - 2;
     const int nruns = 1 << (SL.lx + SL.ly + runs_z_log);
-    const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
+    const int pitch = G.pitch, sxy = G.e[1] * G.pitch;
+    // LDS cell index of input cell i: (i - lo) . (sxy, pitch, 1), evaluated in
+    // FP32 (full-rate FMA) on integer values below 2^24, hence exactly
+    const float lo_f[3] = {(float)G.lo[0], (float)G.lo[1], (float)G.lo[2]};
+    const float sxy_f = (float)sxy, pitch_f = (float)pitch;
     const int8_t lfill = (int8_t)J.label_fill;
 
     for (int r = threadIdx.x; r < nruns; r += kThreads) {
@@ -97,10 +101,8 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                 if (PATH == kPathLdsBoundary && !in_guard(qx, qy, qz, J.nx, J.ny, J.nz))
                     continue;
                 const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-                const int base = (int)mul24(mul24((uint32_t)((int)fx - G.lo[0]), (uint32_t)ey) +
-                                                (uint32_t)((int)fy - G.lo[1]),
-                                            (uint32_t)pitch) +
-                                 ((int)fz - G.lo[2]);
+                const int base = (int)__builtin_fmaf(
+                    fx - lo_f[0], sxy_f, __builtin_fmaf(fy - lo_f[1], pitch_f, fz - lo_f[2]));
                 float kk[8];
                 kk[0] = (float)s_img[base];
                 kk[1] = (float)s_img[base + 1];
@@ -112,10 +114,11 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                 kk[7] = (float)s_img[base + sxy + pitch + 1];
                 V[k] = tri(kk, qx - fx, qy - fy, qz - fz);
                 if (labels) {
-                    const int jx = nn_index(qx) - G.lo[0], jy = nn_index(qy) - G.lo[1],
-                              jz = nn_index(qz) - G.lo[2];
-                    L[k] = s_lbl[mul24(mul24((uint32_t)jx, (uint32_t)ey) + (uint32_t)jy,
-                                       (uint32_t)pitch) + jz];
+                    // nearest voxel floorf(q + 0.5f) (as nn_index), indexed as above
+                    const float jx = floorf(qx + 0.5f), jy = floorf(qy + 0.5f),
+                                jz = floorf(qz + 0.5f);
+                    L[k] = s_lbl[(int)__builtin_fmaf(
+                        jx - lo_f[0], sxy_f, __builtin_fmaf(jy - lo_f[1], pitch_f, jz - lo_f[2]))];
                 }
             } else {
                 if (PATH == kPathDirectInterior) {
@@ -317,6 +320,23 @@ __global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, i
     fwd_tile<T, ALIGNED, DISP>(J, t, TL, lds_cells, s_footprint);
 }
 
+// Index of the job holding global tile t: the number of i in [1, njobs) with
+// prefix[i] <= t (the prefix is nondecreasing), 64 entries per step with one
+// vector load and a ballot, so that a workgroup finds its job in one memory
+// round trip (for up to 64 jobs) rather than one per job passed over.  The
+// count is the same on every lane; it is returned as a scalar.
+__device__ __forceinline__ int job_of(const int32_t *__restrict__ prefix, int njobs, int t)
+{
+    int j = 0;
+    const int lane = threadIdx.x & 63;
+    for (int base = 1; base < njobs; base += 64) {
+        const int i = base + lane;
+        const bool le = i < njobs && prefix[i] <= t;
+        j += __popcll(__ballot(le));
+    }
+    return __builtin_amdgcn_readfirstlane(j);
+}
+
 // Batch of jobs from a device table.  prefix[j] = first global tile of job j,
 // prefix[njobs] = total.  Workgroups stride over the tiles of their XCD's
 // contiguous range (persistent when gridDim.x is a few per CU).  MODE fixes
@@ -335,10 +355,8 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
     const int per = (total + 7) >> 3;
     const int start = xcd * per;
     const int end = min(start + per, total);
-    int j = 0;
     for (int t = start + (b >> 3); t < end; t += per_xcd_wg) {
-        while (j + 1 < njobs && prefix[j + 1] <= t)
-            ++j;
+        const int j = job_of(prefix, njobs, t);
         const FwdJob J = jobs[j];
         const int lt = t - prefix[j];
         if constexpr (MODE == kBatchSplineI16) {
