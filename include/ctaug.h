@@ -94,6 +94,7 @@ typedef struct {
 
 #define CTAUG_PHOTO_WINDOW 1u   /* apply window [win_lo, win_hi] -> [0,1] and gamma */
 #define CTAUG_PHOTO_OCCLUDE 2u  /* random occlusion of the output slab occ_lo <= z <= occ_hi */
+#define CTAUG_PHOTO_NONE 0x80000000u  /* in a job descriptor: no photometric chain */
 
 /* Photometric parameters of one volume (Sec. "GPU-accelerated data
  * augmentation", occlusion, noise and window paragraphs; gain, offset and
@@ -274,6 +275,38 @@ ctaug_status ctaug_warp_affine_backward_noalloc(const ctaug_vol *img_in, const f
                                                 const ctaug_vol *grad_out, ctaug_vol *grad_img,
                                                 double *grad_M, void *stream);
 
+/* Batched adjoint of the affine warp (an addition: one launch for a training
+ * batch's volumes rather than one per volume, so that the per-launch ramp,
+ * tail and reduction are paid once).  Job k holds exactly the arguments of
+ * ctaug_warp_affine_backward for one volume: grad_img.data == NULL means no
+ * image gradient, grad_M == NULL no parameter gradient, photo.flags with
+ * CTAUG_PHOTO_NONE no photometric chain.  Results: as one call per job;
+ * grad_img sums are exact within an output tile and meet in FP32 atomics,
+ * grad_M is reduced in FP64 in a fixed order over the launch's workgroups
+ * (deterministic for a given device and batch; its rounding may differ from
+ * the single call's, which reduces over a different set of rows).  Every
+ * input image must have the same dtype (EDTYPE otherwise); output volumes
+ * of different jobs must not overlap.  Up to 8 jobs go into one launch
+ * (their descriptors travel in the kernel arguments: no upload, no
+ * allocation, graph-capturable); larger batches take one launch per 8.
+ * ws: device workspace of ctaug_warp_affine_backward_batch_workspace(n_jobs)
+ * bytes (FP64 partial rows), required when any job wants grad_M.
+ * Errors: EINVAL (null pointer, n_jobs < 1, bad job), EDTYPE, ESHAPE,
+ * EWORKSPACE, EHIP. */
+typedef struct {
+    ctaug_vol img_in;      /* device F32 / I16, may be strided */
+    ctaug_vol grad_out;    /* device F32, the forward output's dims */
+    ctaug_vol grad_img;    /* device F32, img_in's dims, accumulated into; data NULL = none */
+    double *grad_M;        /* device double[12], overwritten; NULL = none */
+    float M[12];
+    float fill;
+    ctaug_photo photo;     /* without WINDOW; flags CTAUG_PHOTO_NONE = none */
+} ctaug_bwd_job;
+
+size_t ctaug_warp_affine_backward_batch_workspace(int32_t n_jobs);
+ctaug_status ctaug_warp_affine_backward_batch(const ctaug_bwd_job *jobs, int32_t n_jobs,
+                                              void *ws, size_t ws_bytes, void *stream);
+
 /* Adjoint of ctaug_warp_displacement: as above (photo likewise), plus
  * grad_disp[i](p) = g(p) dV/dq_i(p) (device float SoA [3][Xo][Yo][Zo],
  * overwritten, or NULL). */
@@ -395,7 +428,6 @@ typedef struct {
     int64_t grid[3];
 } ctaug_job;
 
-#define CTAUG_PHOTO_NONE 0x80000000u
 
 /* Launch shape: output tile (voxels along x, y, z; each a power of two, z at
  * least 4, at most 2^14 voxels), the number of resident workgroups per CU for

@@ -51,6 +51,12 @@ class Job(ctypes.Structure):
                 ("grid", ctypes.c_int64 * 3)]
 
 
+class BwdJob(ctypes.Structure):
+    _fields_ = [("img_in", Vol), ("grad_out", Vol), ("grad_img", Vol),
+                ("grad_M", ctypes.c_void_p), ("M", ctypes.c_float * 12), ("fill", ctypes.c_float),
+                ("photo", Photo)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32 * 3), ("wg_per_cu", ctypes.c_int32),
                 ("lds_cells", ctypes.c_int32), ("lds_format", ctypes.c_int32)]
@@ -83,6 +89,9 @@ SIGNATURES = {
                                         _PV, _P, _P, ctypes.c_size_t, _P]),
     "ctaug_warp_affine_backward_noalloc": (_S, [_PV, _PF, ctypes.c_float, ctypes.POINTER(Photo),
                                                 _PV, _PV, _P, _P]),
+    "ctaug_warp_affine_backward_batch_workspace": (ctypes.c_size_t, [ctypes.c_int32]),
+    "ctaug_warp_affine_backward_batch": (_S, [ctypes.POINTER(BwdJob), ctypes.c_int32, _P,
+                                              ctypes.c_size_t, _P]),
     "ctaug_warp_displacement_backward": (_S, [_PV, _PF, _P, ctypes.c_float, ctypes.POINTER(Photo),
                                               _PV, _PV, _P, _P, _P, ctypes.c_size_t, _P]),
     "ctaug_warp_bspline_backward_workspace": (ctypes.c_size_t, [_PI64, _PI64]),

@@ -604,6 +604,58 @@ extern "C" ctaug_status ctaug_warp_displacement_backward(const ctaug_vol *img_in
                          grad_disp, ws, ws_bytes, stream);
 }
 
+extern "C" size_t ctaug_warp_affine_backward_batch_workspace(int32_t n_jobs)
+{
+    if (n_jobs < 1 || n_jobs > (1 << 16))
+        return 0;
+    return (size_t)n_jobs * kBwdMaxRows * 12 * sizeof(double);
+}
+
+extern "C" ctaug_status ctaug_warp_affine_backward_batch(const ctaug_bwd_job *jobs, int32_t n_jobs,
+                                                         void *ws, size_t ws_bytes, void *stream)
+{
+    if (!jobs || n_jobs < 1 || n_jobs > (1 << 16))
+        return CTAUG_EINVAL;
+    std::vector<BwdJob> B(n_jobs);
+    bool any_M = false;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const ctaug_bwd_job &j = jobs[k];
+        ctaug_status st;
+        if ((st = check_vol(&j.img_in, 1u << CTAUG_F32 | 1u << CTAUG_I16, true)) != CTAUG_OK)
+            return st;
+        if ((st = check_vol(&j.grad_out, 1u << CTAUG_F32)) != CTAUG_OK)
+            return st;
+        const bool want_img = j.grad_img.data != nullptr;
+        if (want_img) {
+            if ((st = check_vol(&j.grad_img, 1u << CTAUG_F32)) != CTAUG_OK)
+                return st;
+            if (!same_dims(&j.grad_img, &j.img_in))
+                return CTAUG_ESHAPE;
+        }
+        const bool has_photo = !(j.photo.flags & CTAUG_PHOTO_NONE);
+        if ((st = check_photo_adjoint(has_photo ? &j.photo : nullptr)) != CTAUG_OK)
+            return st;
+        if (j.img_in.dtype != jobs[0].img_in.dtype)
+            return CTAUG_EDTYPE;           // one input dtype per batch
+        ctaug_vol out_like = j.grad_out;   // the gradient plays the part of the output (dims only)
+        FwdJob J;
+        st = make_job(&j.img_in, nullptr, j.M, nullptr, false, j.fill, 0,
+                      has_photo ? &j.photo : nullptr, &out_like, nullptr, kDefaultTiling, J);
+        if (st != CTAUG_OK)
+            return st;
+        J.out = nullptr;
+        B[k].J = J;
+        B[k].g = static_cast<const float *>(j.grad_out.data);
+        B[k].g_img = want_img ? static_cast<float *>(j.grad_img.data) : nullptr;
+        B[k].g_M = j.grad_M;
+        any_M = any_M || j.grad_M;
+    }
+    if (any_M && (!ws || ws_bytes < ctaug_warp_affine_backward_batch_workspace(n_jobs)))
+        return CTAUG_EWORKSPACE;
+    return hip_status(launch_warp_bwd_batch(B.data(), n_jobs, static_cast<double *>(ws),
+                                            as_stream(stream)));
+}
+
 // ---------------------------------------------------------------------------
 // Allocation-free adjoint: ctaug_warp_affine_backward with the grad_M partials
 // (the only scratch memory the affine adjoint uses) in a static device array

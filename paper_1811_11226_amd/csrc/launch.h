@@ -53,6 +53,22 @@ hipError_t launch_warp_bwd(const FwdJob &J, const float *g, float *g_img, float 
                            double *g_M, double *partials, double *ctrl_part, float *g_ctrl,
                            hipStream_t s);
 int64_t ctrl_reduce_doubles(int64_t rows, int64_t nctrl);
+// Batched affine adjoint (all jobs of one input dtype): per job its
+// descriptor (tiles set by the launcher), grad_out, grad_img and grad_M
+// (either may be null); partials: kBwdMaxRows * 12 doubles per job.
+struct BwdJob {
+    FwdJob J;
+    const float *g;
+    float *g_img;
+    double *g_M;
+};
+constexpr int32_t kBwdBatchMax = 8;    // jobs per launch (the table travels in the kernel arguments)
+struct BwdBatch {
+    BwdJob jobs[kBwdBatchMax];
+    int32_t prefix[kBwdBatchMax + 1];
+    int32_t njobs;
+};
+hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials, hipStream_t s);
 bool bwd_spline_eval_ok(const BsplineGeom &B);
 bool bwd_ctrl_fused(const BsplineGeom &B);
 

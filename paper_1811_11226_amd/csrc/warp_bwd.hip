@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -252,6 +253,330 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
     __syncthreads();
 }
 
+// The workgroup's sum of acc[12] (fixed order: wave butterflies, then the
+// four waves in order) written to row[0..11].  Every thread must call it;
+// ends after a barrier.
+__device__ __forceinline__ void write_partial_row(const double (&acc)[12],
+                                                  double (*red)[12], double *row)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        const double sum = wave_sum(acc[i]);
+        if (lane == 0)
+            red[wave][i] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        double sum = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w)
+            sum += red[w][threadIdx.x];
+        row[threadIdx.x] = sum;
+    }
+    __syncthreads();                   // red is reused by the next row
+}
+
+// The adjoint of one 8 x 8 x 16 output tile t of job J, for the calling
+// thread's run (voxels z0 + zr + 4k of row (xr, yr)): coordinates, the
+// staged footprint, dV/dq and its FP64 parameter sums (into acc), the image
+// adjoint (fixed-point tile sums, flushed with FP32 atomics), the
+// displacement gradient and the control-grid contraction.  Uniform over the
+// workgroup; ends with every LDS read and write of the tile done.
+template <typename T, int DISP>
+__device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
+                                         gconst<float> *disp, int32_t nvox, bool empty_in,
+                                         bool want_ctrl, bool need_dv, const float *__restrict__ g,
+                                         float *__restrict__ g_img, float *__restrict__ g_disp,
+                                         float *s_ctrl, int32_t lds_cells, int zr, int yr, int xr,
+                                         double (&acc)[12], int (*s_red)[6], float *s_gmax)
+{
+    const Tiling TL = kBwdTiling;
+    const int tz = t % J.tiles_z, rest = t / J.tiles_z;
+    const int ty = rest % J.tiles_y, tx = rest / J.tiles_y;
+    const int x0 = tx << TL.lx, y0 = ty << TL.ly, z0 = tz << TL.lz;
+    const int x1 = min(x0 + (1 << TL.lx), J.ox) - 1, y1 = min(y0 + (1 << TL.ly), J.oy) - 1,
+              z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
+    const int x = x0 + xr, y = y0 + yr, z = z0 + zr;
+    const bool run_ok = x <= x1 && y <= y1 && z <= z1;
+    const int nvalid = run_ok ? min(4, (z1 - z) / 4 + 1) : 0;
+    const int32_t v0 = run_ok ? (x * J.oy + y) * J.oz + z : 0;
+    // coordinates, guard and upstream gradient of the run's voxels
+    float qv[4][3], gpk[4];
+    bool gd[4];
+    float u[3][4];
+    if (DISP == kDispSpline)
+        spline_tile_u<kThreads, false>(J.ctrl, J.bs, TL.lx, TL.ly, x0, y0, z0, x1, y1, z1,
+                                       threadIdx.x >> 2, x, y, z, 4, nvalid, run_ok,
+                                       s_cells, u);
+    {
+        float rb[3];
+        row_base(J.M, (float)x, (float)y, rb);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            gd[k] = false;
+            gpk[k] = 0.0f;
+            qv[k][0] = qv[k][1] = qv[k][2] = 0.0f;
+            if (k >= nvalid)
+                continue;
+            const int32_t v = v0 + 4 * k;
+            const float zf = (float)(z + 4 * k);
+            float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
+                  qz = coord(J.M, 2, rb, zf);
+            if (DISP == kDispField) {
+                qx = qx + disp[v];
+                qy = qy + disp[nvox + v];
+                qz = qz + disp[2 * nvox + v];
+            } else if (DISP == kDispSpline) {
+                qx = qx + u[0][k];
+                qy = qy + u[1][k];
+                qz = qz + u[2][k];
+            }
+            qv[k][0] = qx;
+            qv[k][1] = qy;
+            qv[k][2] = qz;
+            gd[k] = !empty_in && in_guard(qx, qy, qz, J.nx, J.ny, J.nz);
+            // adjoint of the photometric chain without window: the output
+            // is gain * V + offset + sigma * n off the occluded slab and
+            // does not depend on V on it
+            float gv = g[v];
+            if (J.flags & kFlagPhoto) {
+                gv = J.gain * gv;
+                if ((J.flags & kFlagOcclude) && zf >= J.occ_lo && zf <= J.occ_hi)
+                    gv = 0.0f;
+            }
+            gpk[k] = gv;
+        }
+    }
+    TileGeom G;
+    if (DISP != kDispNone) {
+        // no a-priori bound with a displacement field: the footprint is the
+        // range of floor(q) over the tile's guarded samples (block reduction)
+        int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (gd[k])
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int f = (int)floorf(qv[k][i]);
+                    fmn[i] = min(fmn[i], f);
+                    fmx[i] = max(fmx[i], f);
+                }
+        block_minmax3(fmn, fmx, s_red);
+        G = geom_from_cells(J, x0, y0, z0, x1, y1, z1, fmn, fmx, lds_cells);
+    } else {
+        G = box_geom(J, x0, y0, z0, x1, y1, z1, lds_cells);
+    }
+    const bool lds = G.lds;
+    const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
+    if (lds && need_dv) {              // the image adjoint alone needs no corner values
+        stage_footprint<T, float>(J, src, G, s_cells, nullptr);
+        __syncthreads();
+    }
+    // per voxel of the run: LDS cell of corner (0,0,0), fractions, upstream gradient
+    int base[4], cx0[4];
+    float tw[4][3], gk[4];
+    bool live[4] = {false, false, false, false};
+    float S[3] = {0.0f, 0.0f, 0.0f}, Sz[3] = {0.0f, 0.0f, 0.0f};
+    float gu[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        gu[k][0] = gu[k][1] = gu[k][2] = 0.0f;
+    if (run_ok) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= nvalid)
+                continue;
+            const int32_t v = v0 + 4 * k;
+            const float zf = (float)(z + 4 * k);
+            const float qx = qv[k][0], qy = qv[k][1], qz = qv[k][2];
+            const float gp = gpk[k];
+            float dV[3] = {0.0f, 0.0f, 0.0f};
+            if (gd[k]) {
+                float K[8], tt[3];
+                if (lds) {
+                    const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+                    // LDS cell (i - lo) . (sxy, pitch, 1) in exact FP32 (integers < 2^24)
+                    const int bs = (int)__builtin_fmaf(
+                        fx - (float)G.lo[0], (float)sxy,
+                        __builtin_fmaf(fy - (float)G.lo[1], (float)pitch, fz - (float)G.lo[2]));
+                    tt[0] = qx - fx;
+                    tt[1] = qy - fy;
+                    tt[2] = qz - fz;
+                    if (need_dv) {
+                        K[0] = s_cells[bs];
+                        K[1] = s_cells[bs + 1];
+                        K[2] = s_cells[bs + pitch];
+                        K[3] = s_cells[bs + pitch + 1];
+                        K[4] = s_cells[bs + sxy];
+                        K[5] = s_cells[bs + sxy + 1];
+                        K[6] = s_cells[bs + sxy + pitch];
+                        K[7] = s_cells[bs + sxy + pitch + 1];
+                        cell_gradient(K, tt, dV);
+                    }
+                    if (g_img) {
+                        live[k] = true;
+                        base[k] = bs;
+                        cx0[k] = (int)fx - G.lo[0];
+                        tw[k][0] = tt[0];
+                        tw[k][1] = tt[1];
+                        tw[k][2] = tt[2];
+                        gk[k] = gp;
+                    }
+                } else {
+                    int32_t i0[3];
+                    corners_checked<T>(src, qx, qy, qz, J.fill, K, tt, i0);
+                    cell_gradient(K, tt, dV);
+                    if (g_img && gp != 0.0f) {
+                        const float wx[2] = {1.0f - tt[0], tt[0]};
+                        const float wy[2] = {1.0f - tt[1], tt[1]};
+                        const float wz[2] = {1.0f - tt[2], tt[2]};
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+#pragma unroll
+                            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                                for (int c = 0; c < 2; ++c) {
+                                    const int32_t cx = i0[0] + a, cy = i0[1] + bb,
+                                                  cz = i0[2] + c;
+                                    // zero contributions are skipped; a non-finite
+                                    // g reaches every in-volume corner (0 * inf and
+                                    // 0 * NaN are NaN), as in the per-corner path
+                                    const float cw = wx[a] * wy[bb] * wz[c] * gp;
+                                    const bool ok = cx >= 0 && cx < J.nx && cy >= 0 &&
+                                                    cy < J.ny && cz >= 0 && cz < J.nz &&
+                                                    cw != 0.0f;
+                                    if (ok)
+                                        unsafeAtomicAdd(g_img + (cx * J.ny + cy) * J.nz + cz,
+                                                        cw);
+                                }
+                    }
+                }
+            }
+            if (DISP != kDispNone && g_disp) {
+                g_disp[v] = gp * dV[0];
+                g_disp[nvox + v] = gp * dV[1];
+                g_disp[2 * nvox + v] = gp * dV[2];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float c = gp * dV[i];
+                gu[k][i] = c;
+                S[i] += c;
+                Sz[i] = __builtin_fmaf(c, zf, Sz[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            acc[4 * i + 0] += (double)x * (double)S[i];
+            acc[4 * i + 1] += (double)y * (double)S[i];
+            acc[4 * i + 2] += (double)Sz[i];
+            acc[4 * i + 3] += (double)S[i];
+        }
+    }
+    if (lds)                           // uniform: no barrier is skipped by part of the group
+        __syncthreads();               // every corner read of the staged image is done
+    if (want_ctrl)                     // before the image scatter: gu dies here
+        ctrl_adjoint_tile(J.bs, x0, y0, z0, x1, y1, z1, threadIdx.x >> 2, zr, gu, s_cells,
+                          s_ctrl);
+    if (lds) {
+        if (g_img) {
+            // the tile's largest |g|; +inf when any g is not finite (NaN
+            // included, which fmaxf alone would drop), which sends the tile
+            // to the per-corner FP32 path below
+            float gm = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (live[k]) {
+                    const float a = fabsf(gk[k]);
+                    gm = a <= 3.40282347e38f ? fmaxf(gm, a) : __builtin_inff();
+                }
+            gm = block_max(gm, s_gmax);
+            // x-planes of 64-bit accumulators that fit the footprint reservation
+            const int planes = (lds_cells >> 1) / sxy;
+            const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
+            if (gm > 0.0f && gm <= 3.40282347e38f && planes > 0) {
+                const int e = ilogbf(gm) + 1;          // gm < 2^e
+                const double S = ldexp(1.0, 50 - e);
+                const double rS = ldexp(1.0, e - 50);
+                long long *s_acc = reinterpret_cast<long long *>(s_cells);
+                for (int sx0 = 0; sx0 < G.e[0]; sx0 += planes) {   // uniform
+                    const int np = min(planes, G.e[0] - sx0);
+                    const int n = np * sxy;                        // a multiple of 4
+                    for (int c = 2 * threadIdx.x; c < n; c += 2 * kThreads)
+                        *reinterpret_cast<f32x4 *>(s_acc + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (!live[k])
+                            continue;
+                        const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
+                        const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
+                        const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            const int px = cx0[k] + a - sx0;
+                            if ((unsigned)px >= (unsigned)np)
+                                continue;
+#pragma unroll
+                            for (int bb = 0; bb < 2; ++bb) {
+                                const float wxy = wx[a] * wy[bb];
+                                unsigned long long *row = reinterpret_cast<unsigned long long *>(
+                                    s_acc + base[k] - cx0[k] * sxy + px * sxy + bb * pitch);
+                                atomicAdd(row, (unsigned long long)to_fixed(wxy * gz0, S));
+                                atomicAdd(row + 1, (unsigned long long)to_fixed(wxy * gz1, S));
+                            }
+                        }
+                        // one voxel's conversions at a time (register pressure)
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    __syncthreads();
+                    // flush: one global atomic per touched in-volume footprint cell
+                    for (int c = threadIdx.x; c < n; c += kThreads) {
+                        const long long v = s_acc[c];
+                        if (v == 0)
+                            continue;
+                        const int row = div_small(c, pitch, rcp_pitch);
+                        const int cz = c - row * pitch;
+                        const int cx = div_small(row, ey, rcp_ey);
+                        const int cy = row - cx * ey;
+                        const int gx = G.lo[0] + sx0 + cx, gy = G.lo[1] + cy,
+                                  gz = G.lo[2] + cz;
+                        if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
+                            (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
+                            unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz,
+                                            (float)((double)v * rS));
+                    }
+                    __syncthreads();   // LDS is reused next
+                }
+            } else if (gm != 0.0f) {
+                // non-finite gradients (or a footprint too large for one
+                // x-plane of accumulators): FP32 global atomics per corner
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (!live[k])
+                        continue;
+                    const int rel = base[k] - cx0[k] * sxy;
+                    const int cy0 = rel / pitch, cz0 = rel - cy0 * pitch;
+                    const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
+                    const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
+                    const float gz[2] = {(1.0f - tw[k][2]) * gk[k], tw[k][2] * gk[k]};
+                    for (int a = 0; a < 2; ++a)
+                        for (int bb = 0; bb < 2; ++bb)
+                            for (int c = 0; c < 2; ++c) {
+                                const int gx = G.lo[0] + cx0[k] + a, gy = G.lo[1] + cy0 + bb,
+                                          gz2 = G.lo[2] + cz0 + c;
+                                if ((unsigned)gx < (unsigned)J.nx &&
+                                    (unsigned)gy < (unsigned)J.ny &&
+                                    (unsigned)gz2 < (unsigned)J.nz)
+                                    unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz2,
+                                                    wx[a] * wy[bb] * gz[c]);
+                            }
+                }
+            }
+        }
+    }
+}
+
 template <typename T, int DISP>
 __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__restrict__ g,
                                                        float *__restrict__ g_img,
@@ -260,7 +585,6 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
                                                        double *__restrict__ ctrl_part,
                                                        int32_t ntiles, int32_t lds_cells)
 {
-    const Tiling TL = kBwdTiling;
     const int b = blockIdx.x;
     const int per_xcd_wg = gridDim.x >> 3;
     const int per = (ntiles + 7) >> 3;
@@ -299,292 +623,9 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
     const int yr = (threadIdx.x >> 2) & 7;
     const int xr = threadIdx.x >> 5;
 
-    for (int t = start + (b >> 3); t < end; t += per_xcd_wg) {
-        const int tz = t % J.tiles_z, rest = t / J.tiles_z;
-        const int ty = rest % J.tiles_y, tx = rest / J.tiles_y;
-        const int x0 = tx << TL.lx, y0 = ty << TL.ly, z0 = tz << TL.lz;
-        const int x1 = min(x0 + (1 << TL.lx), J.ox) - 1, y1 = min(y0 + (1 << TL.ly), J.oy) - 1,
-                  z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
-        const int x = x0 + xr, y = y0 + yr, z = z0 + zr;
-        const bool run_ok = x <= x1 && y <= y1 && z <= z1;
-        const int nvalid = run_ok ? min(4, (z1 - z) / 4 + 1) : 0;
-        const int32_t v0 = run_ok ? (x * J.oy + y) * J.oz + z : 0;
-        // coordinates, guard and upstream gradient of the run's voxels
-        float qv[4][3], gpk[4];
-        bool gd[4];
-        float u[3][4];
-        if (DISP == kDispSpline)
-            spline_tile_u<kThreads, false>(J.ctrl, J.bs, TL.lx, TL.ly, x0, y0, z0, x1, y1, z1,
-                                           threadIdx.x >> 2, x, y, z, 4, nvalid, run_ok,
-                                           s_cells, u);
-        {
-            float rb[3];
-            row_base(J.M, (float)x, (float)y, rb);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                gd[k] = false;
-                gpk[k] = 0.0f;
-                qv[k][0] = qv[k][1] = qv[k][2] = 0.0f;
-                if (k >= nvalid)
-                    continue;
-                const int32_t v = v0 + 4 * k;
-                const float zf = (float)(z + 4 * k);
-                float qx = coord(J.M, 0, rb, zf), qy = coord(J.M, 1, rb, zf),
-                      qz = coord(J.M, 2, rb, zf);
-                if (DISP == kDispField) {
-                    qx = qx + disp[v];
-                    qy = qy + disp[nvox + v];
-                    qz = qz + disp[2 * nvox + v];
-                } else if (DISP == kDispSpline) {
-                    qx = qx + u[0][k];
-                    qy = qy + u[1][k];
-                    qz = qz + u[2][k];
-                }
-                qv[k][0] = qx;
-                qv[k][1] = qy;
-                qv[k][2] = qz;
-                gd[k] = !empty_in && in_guard(qx, qy, qz, J.nx, J.ny, J.nz);
-                // adjoint of the photometric chain without window: the output
-                // is gain * V + offset + sigma * n off the occluded slab and
-                // does not depend on V on it
-                float gv = g[v];
-                if (J.flags & kFlagPhoto) {
-                    gv = J.gain * gv;
-                    if ((J.flags & kFlagOcclude) && zf >= J.occ_lo && zf <= J.occ_hi)
-                        gv = 0.0f;
-                }
-                gpk[k] = gv;
-            }
-        }
-        TileGeom G;
-        if (DISP != kDispNone) {
-            // no a-priori bound with a displacement field: the footprint is the
-            // range of floor(q) over the tile's guarded samples (block reduction)
-            int fmn[3] = {INT_MAX, INT_MAX, INT_MAX}, fmx[3] = {INT_MIN, INT_MIN, INT_MIN};
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (gd[k])
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const int f = (int)floorf(qv[k][i]);
-                        fmn[i] = min(fmn[i], f);
-                        fmx[i] = max(fmx[i], f);
-                    }
-            block_minmax3(fmn, fmx, s_red);
-            G = geom_from_cells(J, x0, y0, z0, x1, y1, z1, fmn, fmx, lds_cells);
-        } else {
-            G = box_geom(J, x0, y0, z0, x1, y1, z1, lds_cells);
-        }
-        const bool lds = G.lds;
-        const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
-        if (lds && need_dv) {              // the image adjoint alone needs no corner values
-            stage_footprint<T, float>(J, src, G, s_cells, nullptr);
-            __syncthreads();
-        }
-        // per voxel of the run: LDS cell of corner (0,0,0), fractions, upstream gradient
-        int base[4], cx0[4];
-        float tw[4][3], gk[4];
-        bool live[4] = {false, false, false, false};
-        float S[3] = {0.0f, 0.0f, 0.0f}, Sz[3] = {0.0f, 0.0f, 0.0f};
-        float gu[4][3];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            gu[k][0] = gu[k][1] = gu[k][2] = 0.0f;
-        if (run_ok) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (k >= nvalid)
-                    continue;
-                const int32_t v = v0 + 4 * k;
-                const float zf = (float)(z + 4 * k);
-                const float qx = qv[k][0], qy = qv[k][1], qz = qv[k][2];
-                const float gp = gpk[k];
-                float dV[3] = {0.0f, 0.0f, 0.0f};
-                if (gd[k]) {
-                    float K[8], tt[3];
-                    if (lds) {
-                        const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-                        // LDS cell (i - lo) . (sxy, pitch, 1) in exact FP32 (integers < 2^24)
-                        const int bs = (int)__builtin_fmaf(
-                            fx - (float)G.lo[0], (float)sxy,
-                            __builtin_fmaf(fy - (float)G.lo[1], (float)pitch, fz - (float)G.lo[2]));
-                        tt[0] = qx - fx;
-                        tt[1] = qy - fy;
-                        tt[2] = qz - fz;
-                        if (need_dv) {
-                            K[0] = s_cells[bs];
-                            K[1] = s_cells[bs + 1];
-                            K[2] = s_cells[bs + pitch];
-                            K[3] = s_cells[bs + pitch + 1];
-                            K[4] = s_cells[bs + sxy];
-                            K[5] = s_cells[bs + sxy + 1];
-                            K[6] = s_cells[bs + sxy + pitch];
-                            K[7] = s_cells[bs + sxy + pitch + 1];
-                            cell_gradient(K, tt, dV);
-                        }
-                        if (g_img) {
-                            live[k] = true;
-                            base[k] = bs;
-                            cx0[k] = (int)fx - G.lo[0];
-                            tw[k][0] = tt[0];
-                            tw[k][1] = tt[1];
-                            tw[k][2] = tt[2];
-                            gk[k] = gp;
-                        }
-                    } else {
-                        int32_t i0[3];
-                        corners_checked<T>(src, qx, qy, qz, J.fill, K, tt, i0);
-                        cell_gradient(K, tt, dV);
-                        if (g_img && gp != 0.0f) {
-                            const float wx[2] = {1.0f - tt[0], tt[0]};
-                            const float wy[2] = {1.0f - tt[1], tt[1]};
-                            const float wz[2] = {1.0f - tt[2], tt[2]};
-#pragma unroll
-                            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                                for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-                                    for (int c = 0; c < 2; ++c) {
-                                        const int32_t cx = i0[0] + a, cy = i0[1] + bb,
-                                                      cz = i0[2] + c;
-                                        // zero contributions are skipped; a non-finite
-                                        // g reaches every in-volume corner (0 * inf and
-                                        // 0 * NaN are NaN), as in the per-corner path
-                                        const float cw = wx[a] * wy[bb] * wz[c] * gp;
-                                        const bool ok = cx >= 0 && cx < J.nx && cy >= 0 &&
-                                                        cy < J.ny && cz >= 0 && cz < J.nz &&
-                                                        cw != 0.0f;
-                                        if (ok)
-                                            unsafeAtomicAdd(g_img + (cx * J.ny + cy) * J.nz + cz,
-                                                            cw);
-                                    }
-                        }
-                    }
-                }
-                if (DISP != kDispNone && g_disp) {
-                    g_disp[v] = gp * dV[0];
-                    g_disp[nvox + v] = gp * dV[1];
-                    g_disp[2 * nvox + v] = gp * dV[2];
-                }
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const float c = gp * dV[i];
-                    gu[k][i] = c;
-                    S[i] += c;
-                    Sz[i] = __builtin_fmaf(c, zf, Sz[i]);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                acc[4 * i + 0] += (double)x * (double)S[i];
-                acc[4 * i + 1] += (double)y * (double)S[i];
-                acc[4 * i + 2] += (double)Sz[i];
-                acc[4 * i + 3] += (double)S[i];
-            }
-        }
-        if (lds)                           // uniform: no barrier is skipped by part of the group
-            __syncthreads();               // every corner read of the staged image is done
-        if (want_ctrl)                     // before the image scatter: gu dies here
-            ctrl_adjoint_tile(J.bs, x0, y0, z0, x1, y1, z1, threadIdx.x >> 2, zr, gu, s_cells,
-                              s_ctrl);
-        if (lds) {
-            if (g_img) {
-                // the tile's largest |g|; +inf when any g is not finite (NaN
-                // included, which fmaxf alone would drop), which sends the tile
-                // to the per-corner FP32 path below
-                float gm = 0.0f;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (live[k]) {
-                        const float a = fabsf(gk[k]);
-                        gm = a <= 3.40282347e38f ? fmaxf(gm, a) : __builtin_inff();
-                    }
-                gm = block_max(gm, s_gmax);
-                // x-planes of 64-bit accumulators that fit the footprint reservation
-                const int planes = (lds_cells >> 1) / sxy;
-                const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
-                if (gm > 0.0f && gm <= 3.40282347e38f && planes > 0) {
-                    const int e = ilogbf(gm) + 1;          // gm < 2^e
-                    const double S = ldexp(1.0, 50 - e);
-                    const double rS = ldexp(1.0, e - 50);
-                    long long *s_acc = reinterpret_cast<long long *>(s_cells);
-                    for (int sx0 = 0; sx0 < G.e[0]; sx0 += planes) {   // uniform
-                        const int np = min(planes, G.e[0] - sx0);
-                        const int n = np * sxy;                        // a multiple of 4
-                        for (int c = 2 * threadIdx.x; c < n; c += 2 * kThreads)
-                            *reinterpret_cast<f32x4 *>(s_acc + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                        __syncthreads();
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            if (!live[k])
-                                continue;
-                            const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
-                            const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
-                            const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
-#pragma unroll
-                            for (int a = 0; a < 2; ++a) {
-                                const int px = cx0[k] + a - sx0;
-                                if ((unsigned)px >= (unsigned)np)
-                                    continue;
-#pragma unroll
-                                for (int bb = 0; bb < 2; ++bb) {
-                                    const float wxy = wx[a] * wy[bb];
-                                    unsigned long long *row = reinterpret_cast<unsigned long long *>(
-                                        s_acc + base[k] - cx0[k] * sxy + px * sxy + bb * pitch);
-                                    atomicAdd(row, (unsigned long long)to_fixed(wxy * gz0, S));
-                                    atomicAdd(row + 1, (unsigned long long)to_fixed(wxy * gz1, S));
-                                }
-                            }
-                            // one voxel's conversions at a time (register pressure)
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                        __syncthreads();
-                        // flush: one global atomic per touched in-volume footprint cell
-                        for (int c = threadIdx.x; c < n; c += kThreads) {
-                            const long long v = s_acc[c];
-                            if (v == 0)
-                                continue;
-                            const int row = div_small(c, pitch, rcp_pitch);
-                            const int cz = c - row * pitch;
-                            const int cx = div_small(row, ey, rcp_ey);
-                            const int cy = row - cx * ey;
-                            const int gx = G.lo[0] + sx0 + cx, gy = G.lo[1] + cy,
-                                      gz = G.lo[2] + cz;
-                            if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
-                                (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
-                                unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz,
-                                                (float)((double)v * rS));
-                        }
-                        __syncthreads();   // LDS is reused next
-                    }
-                } else if (gm != 0.0f) {
-                    // non-finite gradients (or a footprint too large for one
-                    // x-plane of accumulators): FP32 global atomics per corner
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        if (!live[k])
-                            continue;
-                        const int rel = base[k] - cx0[k] * sxy;
-                        const int cy0 = rel / pitch, cz0 = rel - cy0 * pitch;
-                        const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
-                        const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
-                        const float gz[2] = {(1.0f - tw[k][2]) * gk[k], tw[k][2] * gk[k]};
-                        for (int a = 0; a < 2; ++a)
-                            for (int bb = 0; bb < 2; ++bb)
-                                for (int c = 0; c < 2; ++c) {
-                                    const int gx = G.lo[0] + cx0[k] + a, gy = G.lo[1] + cy0 + bb,
-                                              gz2 = G.lo[2] + cz0 + c;
-                                    if ((unsigned)gx < (unsigned)J.nx &&
-                                        (unsigned)gy < (unsigned)J.ny &&
-                                        (unsigned)gz2 < (unsigned)J.nz)
-                                        unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz2,
-                                                        wx[a] * wy[bb] * gz[c]);
-                                }
-                    }
-                }
-            }
-        }
-    }
+    for (int t = start + (b >> 3); t < end; t += per_xcd_wg)
+        bwd_tile<T, DISP>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, g, g_img, g_disp,
+                          s_ctrl, lds_cells, zr, yr, xr, acc, s_red, s_gmax);
 
     if (want_ctrl)                         // the last tile ended with a barrier
         for (int e = threadIdx.x; e < nctrl; e += kThreads)
@@ -592,6 +633,82 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
 
     if (!partials)
         return;
+    __shared__ double red[kThreads / 64][12];
+    write_partial_row(acc, red, partials + (int64_t)blockIdx.x * 12);
+}
+
+// Batched adjoint: the tiles of up to kBwdBatchMax jobs in one persistent
+// launch, the job table passed by value in the kernel arguments (no upload,
+// nothing to allocate).  prefix[j] = first global tile of job j,
+// prefix[njobs] = total; workgroups stride over their XCD's contiguous tile
+// range, so the jobs a workgroup meets come in increasing order.  The
+// workgroup's FP64 parameter sums of job j go to partials row
+// j * gridDim.x + b (rows of jobs it never meets stay as zeroed before).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_warp_bwd_batch(const BwdBatch B,
+                                                             double *__restrict__ partials,
+                                                             int32_t lds_cells)
+{
+    const int total = B.prefix[B.njobs];
+    const int b = blockIdx.x;
+    const int per_xcd_wg = gridDim.x >> 3;
+    const int per = (total + 7) >> 3;
+    const int start = (b & 7) * per;
+    const int end = min(start + per, total);
+    __shared__ int s_red[kThreads / 64][6];
+    __shared__ float s_gmax[kThreads / 64];
+    __shared__ double red[kThreads / 64][12];
+    const int zr = threadIdx.x & 3;
+    const int yr = (threadIdx.x >> 2) & 7;
+    const int xr = threadIdx.x >> 5;
+    double acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        acc[i] = 0.0;
+    int jcur = -1;
+    for (int t = start + (b >> 3); t < end; t += per_xcd_wg) {
+        int j = 0;                     // the job holding tile t (uniform)
+        for (int i = 1; i < B.njobs; ++i)
+            j += B.prefix[i] <= t;
+        if (j != jcur) {               // the whole workgroup switches jobs
+            if (jcur >= 0 && B.jobs[jcur].g_M) {
+                write_partial_row(acc, red, partials + ((int64_t)jcur * gridDim.x + b) * 12);
+#pragma unroll
+                for (int i = 0; i < 12; ++i)
+                    acc[i] = 0.0;
+            }
+            jcur = j;
+        }
+        const BwdJob &BJ = B.jobs[j];
+        const Src src = make_src<T>(BJ.J);
+        const bool empty_in = BJ.J.nx == 0 || BJ.J.ny == 0 || BJ.J.nz == 0;
+        bwd_tile<T, kDispNone>(BJ.J, t - B.prefix[j], src, nullptr, BJ.J.ox * BJ.J.oy * BJ.J.oz,
+                               empty_in, false, BJ.g_M != nullptr, BJ.g, BJ.g_img, nullptr,
+                               nullptr, lds_cells, zr, yr, xr, acc, s_red, s_gmax);
+    }
+    if (jcur >= 0 && B.jobs[jcur].g_M)
+        write_partial_row(acc, red, partials + ((int64_t)jcur * gridDim.x + b) * 12);
+}
+
+// grad_M of job blockIdx.x: its rows j * nrows .. (j + 1) * nrows - 1 summed
+// in a fixed order (jobs without grad_M are skipped).
+__global__ __launch_bounds__(kThreads) void k_reduce12_batch(const BwdBatch B,
+                                                             const double *__restrict__ partials,
+                                                             int32_t nrows)
+{
+    double *out = B.jobs[blockIdx.x].g_M;
+    if (!out)
+        return;
+    const double *rows = partials + (int64_t)blockIdx.x * nrows * 12;
+    double acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        acc[i] = 0.0;
+#pragma unroll 4
+    for (int r = threadIdx.x; r < nrows; r += kThreads)   // loads issue ahead; sums keep their order
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            acc[i] += rows[(int64_t)r * 12 + i];
     __shared__ double red[kThreads / 64][12];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -605,8 +722,16 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
         double sum = 0.0;
         for (int w = 0; w < kThreads / 64; ++w)
             sum += red[w][threadIdx.x];
-        partials[(int64_t)blockIdx.x * 12 + threadIdx.x] = sum;
+        out[threadIdx.x] = sum;
     }
+}
+
+// Zero n doubles (rows of partials that a batched adjoint may leave unwritten).
+__global__ __launch_bounds__(kThreads) void k_zero_f64(double *__restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n)
+        p[i] = 0.0;
 }
 
 // Sum n rows of 12 doubles in a fixed order into out[12].
@@ -837,6 +962,68 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
         return hipSuccess;
     hipLaunchKernelGGL(k_reduce12, dim3(1), dim3(kThreads), 0, s, partials, grid, g_M);
     return hipGetLastError();
+}
+
+// Batched affine adjoint: chunks of up to kBwdBatchMax jobs, each one
+// persistent launch (its job table in the kernel arguments), a zeroing of
+// its partial rows and one reduction launch.  partials: kBwdMaxRows * 12
+// doubles per job.
+hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials, hipStream_t s)
+{
+    for (int32_t c0 = 0; c0 < n; c0 += kBwdBatchMax) {
+        BwdBatch B;
+        std::memset(&B, 0, sizeof B);
+        B.njobs = std::min<int32_t>(kBwdBatchMax, n - c0);
+        int64_t total = 0;
+        int32_t cells = 64;
+        bool any_M = false;
+        for (int i = 0; i < B.njobs; ++i) {
+            B.jobs[i] = jobs[c0 + i];
+            FwdJob &J = B.jobs[i].J;
+            J.tiles_x = (J.ox + 7) >> 3;
+            J.tiles_y = (J.oy + 7) >> 3;
+            J.tiles_z = (J.oz + 15) >> 4;
+            B.prefix[i] = (int32_t)total;
+            total += (int64_t)J.tiles_x * J.tiles_y * J.tiles_z;
+            if (J.nx > 0 && J.ny > 0 && J.nz > 0 && J.ox > 0 && J.oy > 0 && J.oz > 0)
+                cells = std::max(cells, std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells));
+            any_M = any_M || B.jobs[i].g_M;
+        }
+        B.prefix[B.njobs] = (int32_t)total;
+        double *part = partials + (int64_t)c0 * kBwdMaxRows * 12;
+        const bool i16 = B.jobs[0].J.dtype == kI16;
+        const size_t lds = (size_t)cells * sizeof(float);
+        const void *fn = i16 ? reinterpret_cast<const void *>(&k_warp_bwd_batch<int16_t>)
+                             : reinterpret_cast<const void *>(&k_warp_bwd_batch<float>);
+        const int grid = total > 0 ? bwd_launch_grid(fn, lds, total) : 8;
+        if (any_M) {
+            const int64_t nz = (int64_t)B.njobs * grid * 12;
+            hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((nz + kThreads - 1) / kThreads)),
+                               dim3(kThreads), 0, s, part, nz);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        if (total > 0) {
+            if (i16)
+                hipLaunchKernelGGL(k_warp_bwd_batch<int16_t>, dim3(grid), dim3(kThreads), lds, s, B,
+                                   part, cells);
+            else
+                hipLaunchKernelGGL(k_warp_bwd_batch<float>, dim3(grid), dim3(kThreads), lds, s, B,
+                                   part, cells);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        if (any_M) {
+            hipLaunchKernelGGL(k_reduce12_batch, dim3(B.njobs), dim3(kThreads), 0, s, B, part,
+                               grid);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+    }
+    return hipSuccess;
 }
 
 }  // namespace ctaug

@@ -254,6 +254,46 @@ def warp_affine_backward_noalloc(img, M, grad_out, fill=-1000.0, photo=None, gra
     return grad_img, grad_M
 
 
+def make_bwd_job(img, M, grad_out, grad_img=None, grad_M=None, fill=-1000.0, photo=None):
+    """One job of warp_affine_backward_batch: grad_img (float32, img's dims,
+    accumulated into) and grad_M (float64[12], overwritten) are the caller's
+    tensors, either may be None."""
+    _require(img, "img", (torch.float32, torch.int16), strided=True)
+    _require(grad_out, "grad_out", (torch.float32,))
+    j = _lib.BwdJob()
+    j.img_in = vol(img)
+    j.grad_out = vol(grad_out)
+    j.grad_img = vol(grad_img) if grad_img is not None else _lib.Vol()
+    j.grad_M = grad_M.data_ptr() if grad_M is not None else None
+    j.M = _M32(M)
+    j.fill = float(fill)
+    ph = make_photo(photo)
+    if ph is None:
+        ph = _lib.Photo()
+        ph.flags = CTAUG_PHOTO_NONE
+    j.photo = ph
+    return j
+
+
+def warp_affine_backward_batch(jobs, ws=None):
+    """ctaug_warp_affine_backward_batch over a list of make_bwd_job() jobs (or
+    a ctypes array of them); ws: a uint8 device tensor of at least
+    warp_affine_backward_batch_workspace(len(jobs)) bytes, allocated here
+    when None."""
+    arr = jobs if isinstance(jobs, ctypes.Array) else (_lib.BwdJob * len(jobs))(*jobs)
+    L = _lib.load()
+    need = int(L.ctaug_warp_affine_backward_batch_workspace(len(arr)))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    st = L.ctaug_warp_affine_backward_batch(arr, len(arr), ctypes.c_void_p(ws.data_ptr()),
+                                            ws.numel(), _stream())
+    _lib.check(st, "ctaug_warp_affine_backward_batch")
+
+
+def warp_affine_backward_batch_workspace(n_jobs):
+    return int(_lib.load().ctaug_warp_affine_backward_batch_workspace(int(n_jobs)))
+
+
 def warp_displacement_backward(img, M, disp, grad_out, fill=-1000.0, want_img=True,
                                want_M=True, want_disp=True, photo=None):
     """(grad_img, grad_M, grad_disp)."""

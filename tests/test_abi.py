@@ -576,3 +576,37 @@ def test_noalloc_backward_validation(L):
     assert L.ctaug_warp_affine_backward_noalloc(r(img), mat(), 0.0, None,
                                                 r(vol((0, 4, 4), data=None)), None, None,
                                                 None) == OK
+
+
+def test_batched_backward_validation(L):
+    """The batched adjoint validates every job before anything runs."""
+    r = ctypes.byref
+
+    def job(img_dims=(8, 8, 8), dtype=F32, out_dims=(0, 4, 4), gM=None, **ph):
+        j = _lib.BwdJob()
+        j.img_in = vol(img_dims, dtype)
+        j.grad_out = vol(out_dims, data=None if 0 in out_dims else FAKE)
+        j.grad_img = _lib.Vol()
+        j.grad_M = gM
+        j.M = mat()
+        j.fill = 0.0
+        p = photo(**ph) if ph else photo()
+        if not ph:
+            p.flags = _lib.CTAUG_PHOTO_NONE
+        j.photo = p
+        return j
+
+    arr = lambda *js: (_lib.BwdJob * len(js))(*js)
+    assert L.ctaug_warp_affine_backward_batch_workspace(0) == 0
+    assert L.ctaug_warp_affine_backward_batch_workspace(3) == 3 * 2048 * 12 * 8
+    assert L.ctaug_warp_affine_backward_batch(None, 1, None, 0, None) == EINVAL
+    assert L.ctaug_warp_affine_backward_batch(arr(job()), 0, None, 0, None) == EINVAL
+    # empty outputs, no grad_M: a no-op accepted without a workspace
+    assert L.ctaug_warp_affine_backward_batch(arr(job(), job()), 2, None, 0, None) == OK
+    assert L.ctaug_warp_affine_backward_batch(arr(job(), job(dtype=I16)), 2, None, 0,
+                                              None) == EDTYPE
+    assert L.ctaug_warp_affine_backward_batch(arr(job(gM=FAKE)), 1, None, 0, None) == EWORKSPACE
+    assert L.ctaug_warp_affine_backward_batch(arr(job(flags=1)), 1, None, 0, None) == EINVAL
+    bad = job()
+    bad.grad_img = vol((8, 8, 9))
+    assert L.ctaug_warp_affine_backward_batch(arr(bad), 1, None, 0, None) == ESHAPE

@@ -1175,3 +1175,49 @@ def test_prepared_updates_equal_updates_and_go_stale_on_retuning():
         p.close()
     plan.close()
     ctaug.autotune_cache_clear()
+
+
+@pytest.mark.parametrize("dtype,n", [(np.float32, 10), (np.int16, 3)])
+def test_batched_backward_matches_single_calls_and_oracle(dtype, n):
+    """One batched adjoint launch (two for ten jobs) over volumes of uneven
+    sizes, photometrics on some, a strided input on one: grad_img and grad_M
+    of every job against the single-call adjoint and the oracle; a second
+    batched call gives grad_M bit for bit."""
+    rng = np.random.default_rng(51 + n)
+    items = []
+    for k in range(n):
+        dims = tuple(int(v) for v in rng.integers(20, 48, 3))
+        out_dim = tuple(int(v) for v in rng.integers(16, 44, 3))
+        img, _ = phantom_pair(dims, seed=300 + k)
+        img = img.astype(dtype)
+        prm = draw_affine_params(rng, AugmentRanges(), dims, out_dim)
+        _, M = ctaug.affine_matrix(prm, dims, out_dim)
+        ph = None
+        if k % 3 == 1:
+            ph = draw_photo(rng, AugmentRanges(window=False), seed=k, volume_id=k)
+            ph.occlude, ph.occ_lo, ph.occ_hi = True, 3.0, 7.5
+        g = rng.standard_normal(out_dim).astype(np.float32)
+        if k == 2:                    # a crop view of a larger parent
+            parent = np.zeros((dims[0] + 4, dims[1] + 3, dims[2] + 5), dtype)
+            parent[2:2 + dims[0], 1:1 + dims[1], 3:3 + dims[2]] = img
+            ti = _t(parent)[2:2 + dims[0], 1:1 + dims[1], 3:3 + dims[2]]
+        else:
+            ti = _t(img)
+        items.append((img, ti, M, ph, g, _t(g)))
+    gis = [torch.zeros(it[0].shape, dtype=torch.float32, device=DEV) for it in items]
+    gMs = [torch.empty(12, dtype=torch.float64, device=DEV) for _ in items]
+    jobs = [ctaug.ops.make_bwd_job(ti, M, tg, grad_img=gi, grad_M=gM, photo=ph)
+            for (img, ti, M, ph, g, tg), gi, gM in zip(items, gis, gMs)]
+    ctaug.ops.warp_affine_backward_batch(jobs)
+    first = [_np(gM).copy() for gM in gMs]
+    for k, (img, ti, M, ph, g, tg) in enumerate(items):
+        s_img, s_M = ctaug.warp_affine_backward(ti, M, tg, photo=ph)
+        assert_grad(_np(gis[k]), _np(s_img).astype(np.float64), f"job {k} g_img vs single")
+        np.testing.assert_allclose(first[k], _np(s_M), rtol=1e-12,
+                                   atol=1e-12 * np.abs(_np(s_M)).max())
+        r_img, r_M, _ = oracle.warp_backward(img, M, g, photo=ph)
+        assert_grad(_np(gis[k]), r_img, f"job {k} g_img vs oracle")
+        assert_grad(first[k], r_M, f"job {k} g_M vs oracle")
+    ctaug.ops.warp_affine_backward_batch(jobs)
+    for k, gM in enumerate(gMs):
+        assert np.array_equal(_np(gM).view(np.uint64), first[k].view(np.uint64)), k
