@@ -274,9 +274,10 @@ struct RowWalk {
 // Copy the tile's input footprint into LDS in the LDS cell type (labels as
 // int8), with fill / label_fill in cells outside the volume.  The footprint is
 // e[0] x e[1] rows of `quads` quads of 4 cells (row pitch G.pitch cells).
-// Each row is taken by LPR consecutive lanes (LPR the power of two >= quads,
-// at most 16; a lane takes quads q, q + LPR, ...), so a workgroup covers
-// 256 / LPR rows per pass; rows advance by additions (RowWalk), with no
+// A row of at most 16 quads is taken by `quads` consecutive lanes, one quad
+// each, so a workgroup covers floor(256 / quads) rows per pass with every lane
+// but the last 256 mod quads busy; a longer row is taken by 16 lanes (a lane
+// takes quads q, q + 16, ...).  Rows advance by additions (RowWalk), with no
 // per-quad division or multiplication.  An interior footprint (every quad
 // inside the volume, see box_geom) of at most 16 quads per row is copied
 // without any test: each lane issues the loads of four rows before it
@@ -288,16 +289,27 @@ __device__ __forceinline__ void stage_quads(const FwdJob &J, const Src &S, const
                                             LT *s_img, int8_t *s_lbl)
 {
     const int qpr = G.quads, rows = G.e[0] * G.e[1];
-    const int lpr_log = qpr > 8 ? 4 : qpr > 4 ? 3 : qpr > 2 ? 2 : qpr > 1 ? 1 : 0;
-    const int lpr = 1 << lpr_log;
-    const int ql = threadIdx.x & (lpr - 1);
+    int lpr, ql, row0, rpp;
+    if (qpr <= 16) {
+        // qpr lanes per row, floor(256 / qpr) rows per pass; lanes past the
+        // last whole row stay idle (ql = qpr)
+        lpr = qpr;
+        row0 = div_small(threadIdx.x, qpr, 1.0f / (float)qpr);
+        rpp = kThreads / qpr;
+        ql = row0 < rpp ? threadIdx.x - row0 * qpr : qpr;
+    } else {
+        lpr = 16;
+        row0 = threadIdx.x >> 4;
+        rpp = kThreads >> 4;
+        ql = threadIdx.x & 15;
+    }
     RowWalk W;
-    W.init(S, G, threadIdx.x >> lpr_log, kThreads >> lpr_log, 4 * ql);
+    W.init(S, G, row0, rpp, 4 * min(ql, qpr - 1));
     const bool fast = G.cls == kInterior && G.lo[2] >= 0 && G.lo[2] + 4 * qpr <= J.nz &&
                       qpr <= 16;
     if (fast) {
         if (ql >= qpr)
-            return;                    // lanes beyond the row's quads stay idle
+            return;                    // lanes past the last whole row stay idle
         const int gz0 = G.lo[2] + 4 * ql;
         constexpr int B = 4;           // rows whose loads are in flight together
         for (; W.row < rows;) {

@@ -98,8 +98,18 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                 qz = Q.q[2][k];
             }
             if (PATH == kPathLdsInterior || PATH == kPathLdsBoundary) {
-                if (PATH == kPathLdsBoundary && !in_guard(qx, qy, qz, J.nx, J.ny, J.nz))
-                    continue;
+                // A boundary tile samples without branches: a sample outside the
+                // guard is moved to the footprint's first cell pair (lo .. lo + 1
+                // on each axis, inside every footprint of a box that is not
+                // outside, as box_geom and geom_from_cells make e >= 2), and its
+                // results are replaced by fill / label_fill below.
+                bool guarded = true;
+                if (PATH == kPathLdsBoundary) {
+                    guarded = in_guard(qx, qy, qz, J.nx, J.ny, J.nz);
+                    qx = guarded ? qx : lo_f[0] + 0.25f;
+                    qy = guarded ? qy : lo_f[1] + 0.25f;
+                    qz = guarded ? qz : lo_f[2] + 0.25f;
+                }
                 const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
                 const int base = (int)__builtin_fmaf(
                     fx - lo_f[0], sxy_f, __builtin_fmaf(fy - lo_f[1], pitch_f, fz - lo_f[2]));
@@ -119,6 +129,10 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                                 jz = floorf(qz + 0.5f);
                     L[k] = s_lbl[(int)__builtin_fmaf(
                         jx - lo_f[0], sxy_f, __builtin_fmaf(jy - lo_f[1], pitch_f, jz - lo_f[2]))];
+                }
+                if (PATH == kPathLdsBoundary) {
+                    V[k] = guarded ? V[k] : J.fill;
+                    L[k] = guarded ? L[k] : lfill;
                 }
             } else {
                 if (PATH == kPathDirectInterior) {
