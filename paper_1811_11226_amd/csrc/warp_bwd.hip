@@ -577,8 +577,13 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
     }
 }
 
+// Register budgets follow the LDS: a displacement takes the whole 48 KB
+// reservation (3 workgroups per CU), so at most 168 VGPRs (3 waves per SIMD);
+// an affine job's footprint bound usually keeps a workgroup within 40 KB
+// (4 per CU), so at most 128 VGPRs, a few of them spilled.
 template <typename T, int DISP>
-__global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__restrict__ g,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    DISP == kDispNone ? 4 : 3))) void k_warp_bwd(FwdJob J, const float *__restrict__ g,
                                                        float *__restrict__ g_img,
                                                        float *__restrict__ g_disp,
                                                        double *__restrict__ partials,
@@ -645,7 +650,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_bwd(FwdJob J, const float *__
 // workgroup's FP64 parameter sums of job j go to partials row
 // j * gridDim.x + b (rows of jobs it never meets stay as zeroed before).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_warp_bwd_batch(const BwdBatch B,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_warp_bwd_batch(const BwdBatch B,
                                                              double *__restrict__ partials,
                                                              int32_t lds_cells)
 {
