@@ -1058,7 +1058,7 @@ ctaug_status apply_tiling(ctaug_batch_plan *p, const ctaug_tuning &t)
     p->lds_cells = cells;
     p->total = (int32_t)total;
     ++p->generation;                    // descriptors prepared for the old tiling are stale
-    const int64_t tiles8 = ((total + 7) / 8) * 8;
+    const int64_t tiles8 = 8 * (int64_t)xcd_slots((int)total);
     int64_t grid = t.wg_per_cu > 0 ? (int64_t)p->num_cu * t.wg_per_cu : tiles8;
     grid = std::max<int64_t>(8, (grid / 8) * 8);
     p->grid = (int32_t)std::min<int64_t>(grid, std::max<int64_t>(tiles8, 8));

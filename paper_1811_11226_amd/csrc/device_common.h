@@ -18,6 +18,24 @@ constexpr int kThreads = 256;          // workgroup size of every warp kernel
 constexpr int kRun = 4;                // output voxels per thread along z
 constexpr int kMaxLdsBytes = 61440;    // LDS footprint reservation per workgroup (60 KB)
 
+// XCD-aware tile order.  Consecutive workgroup ids are dispatched round-robin
+// over the 8 XCDs, so workgroup b runs on XCD b % 8.  Tiles are dealt to the
+// XCDs in chunks of 2^kXcdChunkLog consecutive tiles, round-robin, and the
+// workgroups of an XCD take its tiles in increasing order: each XCD (and its
+// L2) gets spatially coherent runs of tiles from every part of the grid, so
+// that jobs of uneven cost spread over all XCDs.  Slot i of XCD x holds tile
+// xcd_tile(x, i); tiles increase with i, and xcd_slots(n) slots per XCD cover
+// n tiles.
+constexpr int kXcdChunkLog = 6;
+__host__ __device__ __forceinline__ int xcd_tile(int xcd, int i)
+{
+    return ((((i >> kXcdChunkLog) << 3) + xcd) << kXcdChunkLog) + (i & ((1 << kXcdChunkLog) - 1));
+}
+__host__ __device__ __forceinline__ int xcd_slots(int n)
+{
+    return ((n + (8 << kXcdChunkLog) - 1) >> (kXcdChunkLog + 3)) << kXcdChunkLog;
+}
+
 enum : uint32_t {
     kFlagWindow = 1u,                  // window + gamma
     kFlagPhoto = 2u,                   // photometric chain enabled

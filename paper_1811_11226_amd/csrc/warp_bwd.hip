@@ -37,8 +37,8 @@
 namespace ctaug {
 
 // Launch shape of the backward pass: 8 x 8 x 16 voxel tiles (one run of 4 z
-// voxels per thread), persistent workgroups striding over their XCD's tile
-// range, and at most kBwdLdsCells FP32 cells of input footprint per
+// voxels per thread), persistent workgroups striding over their XCD's tiles
+// (xcd_tile), and at most kBwdLdsCells FP32 cells of input footprint per
 // workgroup (48 KB of LDS), used first for the staged image, then as the
 // adjoint accumulators of the same cells.
 constexpr Tiling kBwdTiling = {3, 3, 4};
@@ -592,9 +592,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 {
     const int b = blockIdx.x;
     const int per_xcd_wg = gridDim.x >> 3;
-    const int per = (ntiles + 7) >> 3;
-    const int start = (b & 7) * per;
-    const int end = min(start + per, ntiles);
     const Src src = make_src<T>(J);
     gconst<float> *disp = gc<float>(J.disp);
     const int32_t nvox = J.ox * J.oy * J.oz;
@@ -628,9 +625,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int yr = (threadIdx.x >> 2) & 7;
     const int xr = threadIdx.x >> 5;
 
-    for (int t = start + (b >> 3); t < end; t += per_xcd_wg)
+    for (int i = b >> 3;; i += per_xcd_wg) {
+        const int t = xcd_tile(b & 7, i);
+        if (t >= ntiles)
+            break;
         bwd_tile<T, DISP>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, g, g_img, g_disp,
                           s_ctrl, lds_cells, zr, yr, xr, acc, s_red, s_gmax);
+    }
 
     if (want_ctrl)                         // the last tile ended with a barrier
         for (int e = threadIdx.x; e < nctrl; e += kThreads)
@@ -645,8 +646,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 // Batched adjoint: the tiles of up to kBwdBatchMax jobs in one persistent
 // launch, the job table passed by value in the kernel arguments (no upload,
 // nothing to allocate).  prefix[j] = first global tile of job j,
-// prefix[njobs] = total; workgroups stride over their XCD's contiguous tile
-// range, so the jobs a workgroup meets come in increasing order.  The
+// prefix[njobs] = total; workgroups stride over their XCD's tiles in
+// increasing order (xcd_tile), so the jobs a workgroup meets come in
+// increasing order.  The
 // workgroup's FP64 parameter sums of job j go to partials row
 // j * gridDim.x + b (rows of jobs it never meets stay as zeroed before).
 template <typename T>
@@ -657,9 +659,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const int total = B.prefix[B.njobs];
     const int b = blockIdx.x;
     const int per_xcd_wg = gridDim.x >> 3;
-    const int per = (total + 7) >> 3;
-    const int start = (b & 7) * per;
-    const int end = min(start + per, total);
     __shared__ int s_red[kThreads / 64][6];
     __shared__ float s_gmax[kThreads / 64];
     __shared__ double red[kThreads / 64][12];
@@ -671,7 +670,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
     int jcur = -1;
-    for (int t = start + (b >> 3); t < end; t += per_xcd_wg) {
+    for (int i = b >> 3;; i += per_xcd_wg) {
+        const int t = xcd_tile(b & 7, i);
+        if (t >= total)
+            break;
         int j = 0;                     // the job holding tile t (uniform)
         for (int i = 1; i < B.njobs; ++i)
             j += B.prefix[i] <= t;
@@ -890,7 +892,7 @@ static int resident_groups(const void *fn, size_t lds)
 }
 
 // Persistent grid: at most one wave of resident workgroups (a multiple of 8,
-// for the XCD-contiguous tile ranges), at most the workspace's rows.
+// as the XCD tile order assumes), at most the workspace's rows.
 static int bwd_launch_grid(const void *fn, size_t lds, int64_t ntiles)
 {
     const int64_t rows = bwd_grid(ntiles);

@@ -15,10 +15,10 @@
 //   boundary -- per-sample guard and per-corner fill substitution.
 // The three paths compute identical values where they overlap.
 //
-// Workgroup-to-tile mapping is XCD-aware: consecutive workgroup ids are
-// dispatched round-robin over the 8 XCDs, so workgroup b takes tile
-// (b % 8) * ceil(T/8) + b / 8, giving each XCD (and its L2) a contiguous,
-// spatially coherent range of tiles.
+// Workgroup-to-tile mapping is XCD-aware (xcd_tile): consecutive workgroup
+// ids are dispatched round-robin over the 8 XCDs, and tiles are dealt to the
+// XCDs in chunks of consecutive tiles, so that each XCD's L2 sees spatially
+// coherent runs and every XCD gets a share of every job.
 #include "device_common.h"
 #include "launch.h"
 #include "tile_geom.h"
@@ -327,8 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_warp_single(FwdJob J, Tiling TL, i
                                                           int32_t lds_cells)
 {
     const int b = blockIdx.x;
-    const int per = (ntiles + 7) >> 3;
-    const int t = (b & 7) * per + (b >> 3);
+    const int t = xcd_tile(b & 7, b >> 3);
     if (t >= ntiles)
         return;
     fwd_tile<T, ALIGNED, DISP>(J, t, TL, lds_cells, s_footprint);
@@ -352,8 +351,8 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ prefix, int nj
 }
 
 // Batch of jobs from a device table.  prefix[j] = first global tile of job j,
-// prefix[njobs] = total.  Workgroups stride over the tiles of their XCD's
-// contiguous range (persistent when gridDim.x is a few per CU).  MODE fixes
+// prefix[njobs] = total.  Workgroups stride over the tiles of their XCD
+// (xcd_tile; persistent when gridDim.x is a few per CU).  MODE fixes
 // the input and LDS cell types when every job shares them (fewer code paths
 // in the kernel, less register pressure); kBatchMixed dispatches per job.
 template <bool ALIGNED, int MODE>
@@ -366,10 +365,10 @@ __global__ __launch_bounds__(kThreads) void k_warp_batch(const FwdJob *__restric
     const int b = blockIdx.x;
     const int per_xcd_wg = gridDim.x >> 3;
     const int xcd = b & 7;
-    const int per = (total + 7) >> 3;
-    const int start = xcd * per;
-    const int end = min(start + per, total);
-    for (int t = start + (b >> 3); t < end; t += per_xcd_wg) {
+    for (int i = b >> 3;; i += per_xcd_wg) {
+        const int t = xcd_tile(xcd, i);
+        if (t >= total)
+            break;
         const int j = job_of(prefix, njobs, t);
         const FwdJob J = jobs[j];
         const int lt = t - prefix[j];
@@ -502,7 +501,7 @@ hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s
     const int ntiles = J.tiles_x * J.tiles_y * J.tiles_z;
     if (ntiles == 0)
         return hipSuccess;
-    const int grid = ((ntiles + 7) >> 3) << 3;
+    const int grid = 8 * xcd_slots(ntiles);
     const int32_t esz = (J.flags & kFlagLds16) ? 2 : 4;
     const int32_t cells = displaced ? lds_cells_for(kDispLdsCells, esz)
                                  : lds_cells_for(footprint_cells_bound(J, TL), esz);
