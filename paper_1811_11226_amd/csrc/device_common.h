@@ -36,6 +36,24 @@ __host__ __device__ __forceinline__ int xcd_slots(int n)
     return ((n + (8 << kXcdChunkLog) - 1) >> (kXcdChunkLog + 3)) << kXcdChunkLog;
 }
 
+// Slots of one persistent workgroup w of an XCD with W workgroups: in round k
+// it takes slot k W + ((w + 77 k) mod W).  Each round is a permutation of its
+// W slots and a workgroup's slots increase, as with slots w, w + W, ...; the
+// shift keeps a workgroup from meeting the same place of every chunk (the
+// same y-z position of every x slab), whose tiles cost alike.
+struct XcdSlots {
+    int W, skew, pos, base;
+    __device__ __forceinline__ XcdSlots(int w, int nw) : W(nw), skew(77 % nw), pos(w), base(0) {}
+    __device__ __forceinline__ int slot() const { return base + pos; }
+    __device__ __forceinline__ void next()
+    {
+        base += W;
+        pos += skew;
+        if (pos >= W)
+            pos -= W;
+    }
+};
+
 enum : uint32_t {
     kFlagWindow = 1u,                  // window + gamma
     kFlagPhoto = 2u,                   // photometric chain enabled

@@ -625,8 +625,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int yr = (threadIdx.x >> 2) & 7;
     const int xr = threadIdx.x >> 5;
 
-    for (int i = b >> 3;; i += per_xcd_wg) {
-        const int t = xcd_tile(b & 7, i);
+    for (XcdSlots slots(b >> 3, per_xcd_wg);; slots.next()) {
+        const int t = xcd_tile(b & 7, slots.slot());
         if (t >= ntiles)
             break;
         bwd_tile<T, DISP>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, g, g_img, g_disp,
@@ -670,8 +670,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
     int jcur = -1;
-    for (int i = b >> 3;; i += per_xcd_wg) {
-        const int t = xcd_tile(b & 7, i);
+    for (XcdSlots slots(b >> 3, per_xcd_wg);; slots.next()) {
+        const int t = xcd_tile(b & 7, slots.slot());
         if (t >= total)
             break;
         int j = 0;                     // the job holding tile t (uniform)
