@@ -182,6 +182,22 @@ ctaug_status ctaug_warp_affine(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
                                const ctaug_photo *photo, ctaug_vol *img_out,
                                ctaug_vol *lbl_out, void *stream);
 
+/* Nearest-neighbour warp of a label volume alone (Sec. "Pre- and
+ * post-processing": predicted label maps are resampled back to the original
+ * resolution by nearest-neighbour interpolation, with M the map from that
+ * grid into the prediction's).  Per output voxel p with coordinate q = A p + b
+ * in FP32 as ctaug_warp_affine: lbl_out(p) = lbl_in(j), j_i = floorf(q_i +
+ * 0.5f), if q is strictly inside (-1, n) on every axis and j is inside the
+ * volume, else label_fill; bit for bit the labels ctaug_warp_affine writes for
+ * the same M, with no image read or written.  lbl_in: device I8, any dims,
+ * strides allowed (as for gathered inputs).  M: host float[12].  lbl_out:
+ * device I8, dense, output dims; must not alias lbl_in.
+ * Errors: EINVAL (null pointer, non-finite M, reserved != 0, label_fill
+ * outside int8), EDTYPE, ESHAPE (> 2^31-1 elements, a layout beyond the
+ * gather limits), EHIP. */
+ctaug_status ctaug_warp_labels(const ctaug_vol *lbl_in, const float M[12], int32_t label_fill,
+                               ctaug_vol *lbl_out, void *stream);
+
 /* As ctaug_warp_affine with a dense displacement field added to the affine
  * coordinate: q_i = (A p + b)_i + u_i(p) (one FP32 addition).  disp: device
  * float32 SoA [3][Xo][Yo][Zo] on the OUTPUT grid, in input-voxel units.

@@ -76,6 +76,7 @@ SIGNATURES = {
     "ctaug_affine_matrix": (_S, [ctypes.POINTER(AffineParams), _PI64, _PI64, _PD, _PF]),
     "ctaug_warp_affine": (_S, [_PV, _PV, _PF, ctypes.c_float, ctypes.c_int32,
                                ctypes.POINTER(Photo), _PV, _PV, _P]),
+    "ctaug_warp_labels": (_S, [_PV, _PF, ctypes.c_int32, _PV, _P]),
     "ctaug_warp_displacement": (_S, [_PV, _PV, _PF, _P, ctypes.c_float, ctypes.c_int32,
                                      ctypes.POINTER(Photo), _PV, _PV, _P]),
     "ctaug_warp_bspline": (_S, [_PV, _PV, _PF, _P, _PI64, ctypes.c_float, ctypes.c_int32,

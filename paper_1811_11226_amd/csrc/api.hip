@@ -441,6 +441,46 @@ extern "C" ctaug_status ctaug_warp_displacement(const ctaug_vol *img_in, const c
                      stream);
 }
 
+extern "C" ctaug_status ctaug_warp_labels(const ctaug_vol *lbl_in, const float M[12],
+                                          int32_t label_fill, ctaug_vol *lbl_out, void *stream)
+{
+    ctaug_status st;
+    if ((st = check_vol(lbl_in, 1u << CTAUG_I8, true)) != CTAUG_OK)
+        return st;
+    if (!gather_addressable(lbl_in))
+        return CTAUG_ESHAPE;
+    if ((st = check_vol(lbl_out, 1u << CTAUG_I8)) != CTAUG_OK)
+        return st;
+    if (!M || !finite_all(M, 12))
+        return CTAUG_EINVAL;
+    if (label_fill < -128 || label_fill > 127)
+        return CTAUG_EINVAL;
+    FwdJob J;
+    std::memset(&J, 0, sizeof J);
+    J.lbl = static_cast<const int8_t *>(lbl_in->data);
+    J.lout = static_cast<int8_t *>(lbl_out->data);
+    J.dtype = CTAUG_I8;
+    J.nx = (int32_t)lbl_in->dim[0];
+    J.ny = (int32_t)lbl_in->dim[1];
+    J.nz = (int32_t)lbl_in->dim[2];
+    int64_t ry = 0, sy = 0;
+    (void)vol_layout(lbl_in, ry, sy);
+    J.in_ry = (int32_t)ry;
+    J.in_sy = (int32_t)sy;
+    J.in_extent = (int32_t)vol_extent(lbl_in);
+    J.ox = (int32_t)lbl_out->dim[0];
+    J.oy = (int32_t)lbl_out->dim[1];
+    J.oz = (int32_t)lbl_out->dim[2];
+    std::memcpy(J.M, M, sizeof J.M);
+    J.label_fill = label_fill;
+    J.flags = kFlagLabels;
+    if (J.oz % 4 == 0 && (reinterpret_cast<uintptr_t>(J.lout) & 3u) == 0)
+        J.flags |= kFlagVec;
+    if (empty(J))
+        return CTAUG_OK;
+    return hip_status(launch_warp_labels(J, as_stream(stream)));
+}
+
 extern "C" ctaug_status ctaug_warp_bspline(const ctaug_vol *img_in, const ctaug_vol *lbl_in,
                                            const float M[12], const float *ctrl,
                                            const int64_t G[3], float fill, int32_t label_fill,

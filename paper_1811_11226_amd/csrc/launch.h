@@ -9,6 +9,8 @@
 namespace ctaug {
 
 hipError_t launch_warp_single(const FwdJob &J, const Tiling &TL, hipStream_t s);
+// Labels alone (J.lbl, J.lout; J.img unused): see k_warp_labels.
+hipError_t launch_warp_labels(const FwdJob &J, hipStream_t s);
 // Input / LDS cell types shared by every job of a batch launch; the Spline
 // modes warp B-spline jobs (displacement tiles, FP32 LDS cells).
 enum : int { kBatchMixed = 0, kBatchI16F32 = 1, kBatchI16I16 = 2, kBatchF32 = 3,

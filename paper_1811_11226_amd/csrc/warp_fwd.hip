@@ -489,6 +489,68 @@ static_assert(1 << (3 + 3 + 4 - 2) == kThreads, "one run of a displacement tile 
 static_assert(3 * kDispLdsCells >= kSplineTileLdsFloats * (int32_t)sizeof(float),
               "the B-spline scratch of a tile fits its smallest footprint reservation");
 
+// Labels alone: one thread per run of 4 output voxels along z (one packed
+// 4-byte store with kFlagVec), the coordinate and the nearest-neighbour gather
+// of the fused warps (row_base, coord, label_checked), so the labels equal
+// theirs bit for bit.  Runs are numbered z-fastest: run r covers z = 4 (r mod
+// runs_z) .. + 3 of row r / runs_z = x * Yo + y.
+__global__ __launch_bounds__(kThreads) void k_warp_labels(FwdJob J, int32_t runs_z, int64_t nruns)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= nruns)
+        return;
+    const int32_t row = (int32_t)(r / runs_z);
+    const int z = 4 * (int)(r - (int64_t)row * runs_z);
+    const int x = row / J.oy, y = row - x * J.oy;
+    Src S;
+    S.lbl = make_rsrc(J.lbl, (uint32_t)J.in_extent);
+    S.img = S.lbl;                     // not read
+    S.nx = J.nx;
+    S.ny = J.ny;
+    S.nz = J.nz;
+    S.ry = J.in_ry;
+    S.rsy = J.in_sy;
+    S.sy = S.sx = S.sxy = 0;
+    const int8_t lfill = (int8_t)J.label_fill;
+    const bool any_in = J.nx > 0 && J.ny > 0 && J.nz > 0;
+    float rb[3];
+    row_base(J.M, (float)x, (float)y, rb);
+    int8_t L[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        L[k] = lfill;
+        if (!any_in || z + k >= J.oz)
+            continue;
+        const float zf = (float)(z + k);
+        L[k] = label_checked(S, coord(J.M, 0, rb, zf), coord(J.M, 1, rb, zf),
+                             coord(J.M, 2, rb, zf), lfill);
+    }
+    gmut<int8_t> *lout = gm<int8_t>(J.lout);
+    const uint32_t v0 = (uint32_t)row * (uint32_t)J.oz + (uint32_t)z;
+    if (J.flags & kFlagVec) {
+        *reinterpret_cast<gmut<uint32_t> *>(lout + v0) =
+            (uint32_t)(uint8_t)L[0] | ((uint32_t)(uint8_t)L[1] << 8) |
+            ((uint32_t)(uint8_t)L[2] << 16) | ((uint32_t)(uint8_t)L[3] << 24);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (z + k < J.oz)
+                lout[v0 + k] = L[k];
+    }
+}
+
+hipError_t launch_warp_labels(const FwdJob &J, hipStream_t s)
+{
+    const int32_t runs_z = (J.oz + 3) >> 2;
+    const int64_t nruns = (int64_t)J.ox * J.oy * runs_z;
+    if (nruns == 0)
+        return hipSuccess;
+    const int64_t blocks = (nruns + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_warp_labels, dim3((unsigned)blocks), dim3(kThreads), 0, s, J, runs_z,
+                       nruns);
+    return hipGetLastError();
+}
+
 hipError_t launch_warp_single(const FwdJob &J0, const Tiling &TL0, hipStream_t s)
 {
     FwdJob Js = J0;

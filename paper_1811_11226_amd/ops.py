@@ -138,6 +138,21 @@ def warp_affine(img, M, lbl=None, fill=-1000.0, label_fill=0, photo=None, out_di
                  lbl_out)
 
 
+def warp_labels(lbl, M, out_dim=None, label_fill=0, lbl_out=None):
+    """ctaug_warp_labels: nearest-neighbour warp of an int8 label volume alone
+    (no image), equal to warp_affine's labels for the same M.  Returns lbl_out."""
+    _require(lbl, "lbl", (torch.int8,), strided=True)
+    if lbl_out is None:
+        shape = tuple(lbl.shape) if out_dim is None else tuple(out_dim)
+        lbl_out = torch.empty(shape, dtype=torch.int8, device=lbl.device)
+    _require(lbl_out, "lbl_out", (torch.int8,))
+    vi, vo = vol(lbl), vol(lbl_out)
+    st = _lib.load().ctaug_warp_labels(ctypes.byref(vi), _M32(M), int(label_fill),
+                                       ctypes.byref(vo), _stream())
+    _lib.check(st, "ctaug_warp_labels")
+    return lbl_out
+
+
 def warp_displacement(img, M, disp, lbl=None, fill=-1000.0, label_fill=0, photo=None,
                       out=None, lbl_out=None):
     """As warp_affine with a dense displacement disp [3][Xo][Yo][Zo] added."""

@@ -283,6 +283,30 @@ def test_empty_volumes_are_no_ops(L):
     assert L.ctaug_copy(None, None, 0, None) == OK
 
 
+def test_labels_only_warp_validation(L):
+    r = ctypes.byref
+    lin, lout = vol((8, 8, 8), I8), vol((4, 4, 4), I8)
+    assert L.ctaug_warp_labels(None, mat(), 0, r(lout), None) == EINVAL
+    assert L.ctaug_warp_labels(r(lin), mat(), 0, None, None) == EINVAL
+    assert L.ctaug_warp_labels(r(lin), None, 0, r(lout), None) == EINVAL
+    assert L.ctaug_warp_labels(r(lin), mat([math.inf] + [0.0] * 11), 0, r(lout), None) == EINVAL
+    for lf in (-129, 128):
+        assert L.ctaug_warp_labels(r(lin), mat(), lf, r(lout), None) == EINVAL
+    assert L.ctaug_warp_labels(r(vol((8, 8, 8), I16)), mat(), 0, r(lout), None) == EDTYPE
+    assert L.ctaug_warp_labels(r(lin), mat(), 0, r(vol((4, 4, 4))), None) == EDTYPE
+    assert L.ctaug_warp_labels(r(lin), mat(), 0, r(vol((4, -1, 4), I8)), None) == ESHAPE
+    assert L.ctaug_warp_labels(r(vol((8, 8, 8), I8, reserved=1)), mat(), 0, r(lout), None) == EINVAL
+    # a strided input is accepted (a crop view); a strided output is not
+    crop = vol((4, 4, 4), I8, stride=(64, 8, 1))
+    assert L.ctaug_warp_labels(r(crop), mat(), 0, r(vol((0, 4, 4), I8, data=None)), None) == OK
+    assert L.ctaug_warp_labels(r(lin), mat(), 0, r(vol((4, 4, 4), I8, stride=(64, 8, 1))),
+                               None) == ESHAPE
+    # rows beyond the 24-bit gather limit
+    assert L.ctaug_warp_labels(r(vol((2, 1 << 24, 4), I8)), mat(), 0, r(lout), None) == ESHAPE
+    # an empty output is a no-op
+    assert L.ctaug_warp_labels(r(lin), mat(), 0, r(vol((4, 0, 4), I8, data=None)), None) == OK
+
+
 def test_displacement_and_noise_validation(L):
     img, out = ctypes.byref(vol((8, 8, 8), I16)), ctypes.byref(vol((4, 4, 4)))
     assert L.ctaug_warp_displacement(img, None, mat(), None, 0.0, 0, None, out, None,
