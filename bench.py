@@ -725,10 +725,10 @@ def write_traffic(fetch_csv, write_csv, copy_bytes=1 << 30):
     with open(path, "w") as f:
         f.write("# HBM-side traffic of k_warp_batch on the 16-volume 120x120x160 batch\n")
         f.write("# (cd /tmp && export TMPDIR=/tmp)\n")
-        for c in ("FETCH_SIZE", "WRITE_SIZE"):
-            f.write(f"# rocprofv3 --pmc {c} --kernel-include-regex 'k_warp_batch|k_copy16' "
-                    f"--output-format csv -d <dir> -o run -- python3 bench.py --profile "
-                    f"--steps 20 --warmup 2\n")
+        for c in ("FETCH_SIZE", "WRITE_SIZE TCC_HIT_sum TCC_MISS_sum"):
+            f.write(f"# timeout -s KILL 240 rocprofv3 --pmc {c} --kernel-include-regex "
+                    f"'k_warp_batch|k_copy16' --output-format csv -d <dir> -o run -- "
+                    f"python3 bench.py --profile --steps 20 --warmup 2\n")
         f.write("# python3 bench.py --traffic <FETCH_SIZE dir>/run_counter_collection.csv "
                 "<WRITE_SIZE dir>/run_counter_collection.csv\n")
         f.write("# KiB per dispatch (mean over the batched kernel's dispatches) scaled by\n")
