@@ -117,22 +117,6 @@ __device__ __forceinline__ long long to_fixed(float v, double S)
     return __double_as_longlong(d) - __double_as_longlong(kMagic);
 }
 
-__device__ __forceinline__ float block_max(float v, float *s)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v = fmaxf(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x & 63) == 0)
-        s[threadIdx.x >> 6] = v;
-    __syncthreads();
-    float m = s[0];
-#pragma unroll
-    for (int w = 1; w < kThreads / 64; ++w)
-        m = fmaxf(m, s[w]);
-    __syncthreads();
-    return m;
-}
-
 // Spline weight matrix of one tile axis: Wt[p][c] = B_{c - (i(p) - i(p0))}(t(p))
 // for the 2^lp voxels p0 + p <= p1 of the axis and the window of kSplineWindow
 // controls starting at i(p0); 0 elsewhere.  One entry per calling thread.
@@ -368,6 +352,24 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
     }
     const bool lds = G.lds;
     const int ey = G.e[1], pitch = G.pitch, sxy = G.e[1] * G.pitch;
+    if (lds && g_img) {
+        // the tile's largest |g| over its guarded samples: reduced in each
+        // wave here, across the waves after the barrier that ends the corner
+        // reads; +inf when any g is not finite (NaN included, which fmaxf
+        // alone would drop), which sends the tile to the per-corner FP32 path
+        float gw = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (gd[k]) {
+                const float a = fabsf(gpk[k]);
+                gw = a <= 3.40282347e38f ? fmaxf(gw, a) : __builtin_inff();
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            gw = fmaxf(gw, __shfl_xor(gw, off, 64));
+        if ((threadIdx.x & 63) == 0)
+            s_gmax[threadIdx.x >> 6] = gw;
+    }
     if (lds && need_dv) {              // the image adjoint alone needs no corner values
         stage_footprint<T, float>(J, src, G, s_cells, nullptr);
         __syncthreads();
@@ -480,17 +482,12 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                           s_ctrl);
     if (lds) {
         if (g_img) {
-            // the tile's largest |g|; +inf when any g is not finite (NaN
-            // included, which fmaxf alone would drop), which sends the tile
-            // to the per-corner FP32 path below
-            float gm = 0.0f;
+            // the tile's largest |g| (the waves' maxima, written before the
+            // barrier that ended the corner reads)
+            float gm = s_gmax[0];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (live[k]) {
-                    const float a = fabsf(gk[k]);
-                    gm = a <= 3.40282347e38f ? fmaxf(gm, a) : __builtin_inff();
-                }
-            gm = block_max(gm, s_gmax);
+            for (int w = 1; w < kThreads / 64; ++w)
+                gm = fmaxf(gm, s_gmax[w]);
             // x-planes of 64-bit accumulators that fit the footprint reservation
             const int planes = (lds_cells >> 1) / sxy;
             const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
