@@ -43,7 +43,7 @@ C3_OUT = (120, 120, 160)
 # `--autotune` re-runs the sweep on this workload and rewrites the file.
 TUNING_CACHE = os.path.join(ROOT, "paper_1811_11226_amd", "autotune_cache.txt")
 C3_CANDIDATES = [(tile, 0, lds, fmt) for tile in [(8, 16, 16), (16, 16, 16), (16, 16, 32)]
-                 for lds in (0, 6128, 8176, 12272) for fmt in (0, 1)]
+                 for lds in (0, 8176, 10208, 12272) for fmt in (0, 1)]
 
 # VALU roofline.  Peak: 256 CUs x 64 lanes x 2.4 GHz non-packed lane-ops
 # (one FP32/INT32 op per lane per cycle; transcendentals and 32x32->64-bit

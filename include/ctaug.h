@@ -449,10 +449,11 @@ typedef struct {
  * least 4, at most 2^14 voxels), the number of resident workgroups per CU for
  * the persistent launch (0 = one workgroup per tile, non-persistent), and the
  * LDS footprint reserved per workgroup in input cells (0 = sized from the
- * jobs; -1 = no LDS staging), and the cell format: 0 = FP32 cells (5 bytes
- * per cell with the int8 label; at most 12272 cells in the 60 KB
- * reservation), 1 = int16 cells when every input is int16 (3 bytes per cell,
- * at most 20464 cells; half the LDS, more LDS reads).  Tiles whose footprint
+ * jobs; -1 = no LDS staging), and the cell format: 0 = FP32 cells (4 bytes
+ * per cell; at most 15344 cells in the 60 KB reservation), 1 = int16 cells
+ * when every input is int16 (2 bytes per cell, at most 30704 cells; half the
+ * LDS, more conversions per corner read).  Labels are not staged: they are
+ * gathered from global memory while sampling.  Tiles whose footprint
  * exceeds the reservation, and int16-cell jobs whose fill value is not an
  * int16, gather directly from global memory, with identical results. */
 typedef struct {

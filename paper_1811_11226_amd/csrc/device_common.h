@@ -177,12 +177,6 @@ template <> struct Elem<int16_t> {
     }
 };
 
-// Offset of the label array in a footprint reservation of `cells` cells of T.
-template <typename T> __device__ __host__ __forceinline__ uint32_t lds_label_offset(int32_t cells)
-{
-    return ((uint32_t)cells * (uint32_t)sizeof(T) + 15u) & ~15u;
-}
-
 __device__ __forceinline__ int8_t load_i8(rsrc_t r, uint32_t off)
 {
     return (int8_t)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);

@@ -183,52 +183,40 @@ __device__ __forceinline__ int div_small(int a, int b, float rcp_b)
 }
 
 // A quad of four input cells (gx, gy, gz0 .. gz0 + 3) wholly inside the volume,
-// at element offset e: one wide load per array.
-template <typename T, typename LT, bool LBL>
-__device__ __forceinline__ void quad_inside(const Src &S, uint32_t e, LT *dst, int8_t *ldst)
+// at element offset e: one wide load.
+template <typename T, typename LT>
+__device__ __forceinline__ void quad_inside(const Src &S, uint32_t e, LT *dst)
 {
     copy_quad(S.img, e * (uint32_t)sizeof(T), dst, T());
-    if (LBL)
-        *reinterpret_cast<uint32_t *>(ldst) = __builtin_amdgcn_raw_buffer_load_b32(S.lbl, e, 0, 0);
 }
 
 // A quad of an in-volume row (element offset e_row0 of its z = 0 cell) whose
 // z range leaves the volume: each cell is loaded from its z clamped into the
-// volume (every load stays in range) and replaced by fill / label_fill outside.
-template <typename T, typename LT, bool LBL>
+// volume (every load stays in range) and replaced by fill outside.
+template <typename T, typename LT>
 __device__ __forceinline__ void quad_partial(const FwdJob &J, const Src &S, int e_row0, int gz0,
-                                             LT *dst, int8_t *ldst)
+                                             LT *dst)
 {
     constexpr uint32_t es = sizeof(T);
-    const int8_t lfill = (int8_t)J.label_fill;
     const LT tfill = (LT)J.fill;
     LT v[4];
-    uint32_t lp = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int gz = gz0 + u;
         const uint32_t e = (uint32_t)(e_row0 + min(max(gz, 0), J.nz - 1));
         const T raw = Elem<T>::raw(S.img, e * es, 0);
-        const int8_t lab = LBL ? load_i8(S.lbl, e) : lfill;
-        const bool in = (unsigned)gz < (unsigned)J.nz;
-        v[u] = in ? (LT)raw : tfill;
-        if (LBL)
-            lp |= (uint32_t)(uint8_t)(in ? lab : lfill) << (8 * u);
+        v[u] = (unsigned)gz < (unsigned)J.nz ? (LT)raw : tfill;
     }
     store4(dst, v);
-    if (LBL)
-        *reinterpret_cast<uint32_t *>(ldst) = lp;
 }
 
-// A quad of a row outside the volume: fill / label_fill, nothing loaded.
-template <typename LT, bool LBL>
-__device__ __forceinline__ void quad_fill(const FwdJob &J, LT *dst, int8_t *ldst)
+// A quad of a row outside the volume: fill, nothing loaded.
+template <typename LT>
+__device__ __forceinline__ void quad_fill(const FwdJob &J, LT *dst)
 {
     const LT tfill = (LT)J.fill;
     const LT v[4] = {tfill, tfill, tfill, tfill};
     store4(dst, v);
-    if (LBL)
-        *reinterpret_cast<uint32_t *>(ldst) = 0x01010101u * (uint32_t)(uint8_t)(int8_t)J.label_fill;
 }
 
 // Row walk of the footprint staging: the lane takes rows row, row + rpp, ...
@@ -271,8 +259,9 @@ struct RowWalk {
     }
 };
 
-// Copy the tile's input footprint into LDS in the LDS cell type (labels as
-// int8), with fill / label_fill in cells outside the volume.  The footprint is
+// Copy the tile's input image footprint into LDS in the LDS cell type, with
+// fill in cells outside the volume (labels are gathered from global memory
+// while sampling, so that the LDS holds image cells only).  The footprint is
 // e[0] x e[1] rows of `quads` quads of 4 cells (row pitch G.pitch cells).
 // A row of at most 16 quads is taken by `quads` consecutive lanes, one quad
 // each, so a workgroup covers floor(256 / quads) rows per pass with every lane
@@ -284,9 +273,9 @@ struct RowWalk {
 // converts and writes them.  Other footprints test each row and quad: rows
 // outside the volume are filled without loads, quads crossing its z ends
 // load per cell from clamped indices.
-template <typename T, typename LT, bool LBL>
-__device__ __forceinline__ void stage_quads(const FwdJob &J, const Src &S, const TileGeom &G,
-                                            LT *s_img, int8_t *s_lbl)
+template <typename T, typename LT>
+__device__ __forceinline__ void stage_footprint(const FwdJob &J, const Src &S, const TileGeom &G,
+                                                LT *s_img)
 {
     const int qpr = G.quads, rows = G.e[0] * G.e[1];
     int lpr, ql, row0, rpp;
@@ -324,21 +313,14 @@ __device__ __forceinline__ void stage_quads(const FwdJob &J, const Src &S, const
                 W.next();
             }
             typename QuadRaw<T>::type w[B];
-            uint32_t lab[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const uint32_t eu = ok[u] ? e[u] : e[0];    // in the volume either way
-                w[u] = QuadRaw<T>::load(S.img, eu);
-                if (LBL)
-                    lab[u] = __builtin_amdgcn_raw_buffer_load_b32(S.lbl, eu, 0, 0);
-            }
+            for (int u = 0; u < B; ++u)
+                w[u] = QuadRaw<T>::load(S.img, ok[u] ? e[u] : e[0]);   // in the volume either way
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 if (!ok[u])
                     break;
                 QuadRaw<T>::store(w[u], s_img + l[u]);
-                if (LBL)
-                    *reinterpret_cast<uint32_t *>(s_lbl + l[u]) = lab[u];
             }
         }
         return;
@@ -349,25 +331,14 @@ __device__ __forceinline__ void stage_quads(const FwdJob &J, const Src &S, const
         for (int q = ql; q < qpr; q += lpr) {
             const int gz0 = G.lo[2] + 4 * q;
             LT *dst = s_img + W.l_row + 4 * (q - ql);
-            int8_t *ldst = s_lbl + W.l_row + 4 * (q - ql);
             if (!row_in)
-                quad_fill<LT, LBL>(J, dst, ldst);
+                quad_fill<LT>(J, dst);
             else if (gz0 >= 0 && gz0 + 3 < J.nz)
-                quad_inside<T, LT, LBL>(S, (uint32_t)(W.e_row + gz0), dst, ldst);
+                quad_inside<T, LT>(S, (uint32_t)(W.e_row + gz0), dst);
             else
-                quad_partial<T, LT, LBL>(J, S, W.e_row, gz0, dst, ldst);
+                quad_partial<T, LT>(J, S, W.e_row, gz0, dst);
         }
     }
-}
-
-template <typename T, typename LT>
-__device__ __forceinline__ void stage_footprint(const FwdJob &J, const Src &S, const TileGeom &G,
-                                                LT *s_img, int8_t *s_lbl)
-{
-    if (J.flags & kFlagLabels)
-        stage_quads<T, LT, true>(J, S, G, s_img, s_lbl);
-    else
-        stage_quads<T, LT, false>(J, S, G, s_img, s_lbl);
 }
 
 // Workgroup-wide min of mn[] and max of mx[] (3 ints each); every thread gets

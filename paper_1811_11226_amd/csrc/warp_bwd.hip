@@ -371,7 +371,7 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
             s_gmax[threadIdx.x >> 6] = gw;
     }
     if (lds && need_dv) {              // the image adjoint alone needs no corner values
-        stage_footprint<T, float>(J, src, G, s_cells, nullptr);
+        stage_footprint<T, float>(J, src, G, s_cells);
         __syncthreads();
     }
     // per voxel of the run: LDS cell of corner (0,0,0), fractions, upstream gradient

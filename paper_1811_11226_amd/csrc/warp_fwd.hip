@@ -42,7 +42,7 @@ struct RunQ {
 // exactly one run per thread and its coordinates come precomputed in Q.
 template <typename T, typename LT, int PATH, bool ALIGNED, bool LBL, int DISP>
 __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, const Tiling &SL,
-                                         const LT *s_img, const int8_t *s_lbl, const RunQ &Q)
+                                         const LT *s_img, const RunQ &Q)
 {
     const Src S = make_src<T>(J);
     gmut<float> *out = gm<float>(J.out);
@@ -103,6 +103,11 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                 // on each axis, inside every footprint of a box that is not
                 // outside, as box_geom and geom_from_cells make e >= 2), and its
                 // results are replaced by fill / label_fill below.
+                // labels straight from global memory: an interior tile's
+                // nearest voxel is inside the volume
+                if (labels)
+                    L[k] = PATH == kPathLdsInterior ? label_interior(S, qx, qy, qz)
+                                                    : label_checked(S, qx, qy, qz, lfill);
                 bool guarded = true;
                 if (PATH == kPathLdsBoundary) {
                     guarded = in_guard(qx, qy, qz, J.nx, J.ny, J.nz);
@@ -123,17 +128,8 @@ __device__ __forceinline__ void run_tile(const FwdJob &J, const TileGeom &G, con
                 kk[6] = (float)s_img[base + sxy + pitch];
                 kk[7] = (float)s_img[base + sxy + pitch + 1];
                 V[k] = tri(kk, qx - fx, qy - fy, qz - fz);
-                if (labels) {
-                    // nearest voxel floorf(q + 0.5f) (as nn_index), indexed as above
-                    const float jx = floorf(qx + 0.5f), jy = floorf(qy + 0.5f),
-                                jz = floorf(qz + 0.5f);
-                    L[k] = s_lbl[(int)__builtin_fmaf(
-                        jx - lo_f[0], sxy_f, __builtin_fmaf(jy - lo_f[1], pitch_f, jz - lo_f[2]))];
-                }
-                if (PATH == kPathLdsBoundary) {
+                if (PATH == kPathLdsBoundary)
                     V[k] = guarded ? V[k] : J.fill;
-                    L[k] = guarded ? L[k] : lfill;
-                }
             } else {
                 if (PATH == kPathDirectInterior) {
                     V[k] = sample_interior<T>(S, qx, qy, qz);
@@ -199,21 +195,20 @@ __device__ __forceinline__ void fwd_box_l(const FwdJob &J, const TileGeom &G, co
                                          uint8_t *s_lds, int32_t lds_cells, const RunQ &Q)
 {
     LT *s_img = reinterpret_cast<LT *>(s_lds);
-    int8_t *s_lbl = reinterpret_cast<int8_t *>(s_lds + lds_label_offset<LT>(lds_cells));
     if (G.cls == kOutside) {
-        run_tile<T, LT, kPathOutside, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
+        run_tile<T, LT, kPathOutside, ALIGNED, LBL, DISP>(J, G, SL, s_img, Q);
     } else if (G.lds) {
-        stage_footprint<T, LT>(J, make_src<T>(J), G, s_img, s_lbl);
+        stage_footprint<T, LT>(J, make_src<T>(J), G, s_img);
         __syncthreads();
         if (G.cls == kInterior)
-            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
+            run_tile<T, LT, kPathLdsInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, Q);
         else
-            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
+            run_tile<T, LT, kPathLdsBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, Q);
         __syncthreads();               // LDS is reused by the next box
     } else if (G.cls == kInterior) {
-        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
+        run_tile<T, LT, kPathDirectInterior, ALIGNED, LBL, DISP>(J, G, SL, s_img, Q);
     } else {
-        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, s_lbl, Q);
+        run_tile<T, LT, kPathDirectBoundary, ALIGNED, LBL, DISP>(J, G, SL, s_img, Q);
     }
 }
 
@@ -318,7 +313,7 @@ __device__ __forceinline__ void fwd_tile(const FwdJob &J, int t, const Tiling &T
 }
 
 // Dynamic LDS: lds_cells input-type cells of image footprint (rounded up to
-// 16 bytes), then lds_cells int8 labels.
+// 16 bytes); labels are gathered from global memory.
 extern __shared__ __attribute__((aligned(16))) uint8_t s_footprint[];
 
 // Single job, job in kernel arguments, one workgroup per tile.
@@ -451,7 +446,7 @@ Tiling choose_subtile(const FwdJob &J, const Tiling &TL, int32_t lds_cells)
 
 int32_t lds_cells_cap(int32_t elem_bytes)
 {
-    return (kMaxLdsBytes - 16) / (elem_bytes + 1) & ~15;
+    return (kMaxLdsBytes - 16) / elem_bytes & ~15;
 }
 
 int32_t lds_cells_for(int32_t bound, int32_t elem_bytes)
@@ -461,7 +456,7 @@ int32_t lds_cells_for(int32_t bound, int32_t elem_bytes)
 
 size_t lds_bytes_for(int32_t cells, int32_t elem_bytes)
 {
-    return (((size_t)cells * (size_t)elem_bytes + 15) & ~(size_t)15) + (size_t)cells;
+    return ((size_t)cells * (size_t)elem_bytes + 15) & ~(size_t)15;
 }
 
 template <int DISP>
@@ -486,7 +481,7 @@ static void launch_single_t(const FwdJob &J, const Tiling &TL, int ntiles, int32
 }
 
 static_assert(1 << (3 + 3 + 4 - 2) == kThreads, "one run of a displacement tile per thread");
-static_assert(3 * kDispLdsCells >= kSplineTileLdsFloats * (int32_t)sizeof(float),
+static_assert(2 * kDispLdsCells >= kSplineTileLdsFloats * (int32_t)sizeof(float),
               "the B-spline scratch of a tile fits its smallest footprint reservation");
 
 // Labels alone: one thread per run of 4 output voxels along z (one packed
