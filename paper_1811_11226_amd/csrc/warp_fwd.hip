@@ -292,14 +292,40 @@ __device__ __forceinline__ void fwd_tile_lt(const FwdJob &J, int t, const Tiling
         return;
     }
     const RunQ Q0{};
-    for (int sx = x0; sx <= x1; sx += 1 << SL.lx)
-        for (int sy = y0; sy <= y1; sy += 1 << SL.ly)
-            for (int sz = z0; sz <= z1; sz += 1 << SL.lz) {
-                const TileGeom G = box_geom(J, sx, sy, sz, min(sx + (1 << SL.lx) - 1, x1),
-                                            min(sy + (1 << SL.ly) - 1, y1),
-                                            min(sz + (1 << SL.lz) - 1, z1), lds_cells);
-                fwd_box<T, LT, ALIGNED, kDispNone>(J, G, SL, s_lds, lds_cells, Q0);
-            }
+    const int nz = ((z1 - z0) >> SL.lz) + 1, ny = ((y1 - y0) >> SL.ly) + 1,
+              nx = ((x1 - x0) >> SL.lx) + 1;
+    const int nsub = nx * ny * nz;     // sub-boxes, x-major
+    auto geom = [&](int i) {
+        const int iz = i % nz, r = i / nz, iy = r % ny, ix = r / ny;
+        const int sx = x0 + (ix << SL.lx), sy = y0 + (iy << SL.ly), sz = z0 + (iz << SL.lz);
+        return box_geom(J, sx, sy, sz, min(sx + (1 << SL.lx) - 1, x1),
+                        min(sy + (1 << SL.ly) - 1, y1), min(sz + (1 << SL.lz) - 1, z1),
+                        lds_cells);
+    };
+    // the geometry of every sub-box at once, sub-box i in lane i of each wave
+    // (one dependent chain per tile instead of one per box), read per box;
+    // choose_subtile keeps a tile at no more than 16 sub-boxes
+    __builtin_assume(nsub <= 64);
+    const TileGeom Gl = geom(min((int)(threadIdx.x & 63), nsub - 1));
+    for (int i = 0; i < nsub; ++i) {
+        TileGeom G;
+        G.x0 = __builtin_amdgcn_readlane(Gl.x0, i);
+        G.y0 = __builtin_amdgcn_readlane(Gl.y0, i);
+        G.z0 = __builtin_amdgcn_readlane(Gl.z0, i);
+        G.x1 = __builtin_amdgcn_readlane(Gl.x1, i);
+        G.y1 = __builtin_amdgcn_readlane(Gl.y1, i);
+        G.z1 = __builtin_amdgcn_readlane(Gl.z1, i);
+        G.cls = __builtin_amdgcn_readlane(Gl.cls, i);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            G.lo[a] = __builtin_amdgcn_readlane(Gl.lo[a], i);
+            G.e[a] = __builtin_amdgcn_readlane(Gl.e[a], i);
+        }
+        G.quads = __builtin_amdgcn_readlane(Gl.quads, i);
+        G.pitch = __builtin_amdgcn_readlane(Gl.pitch, i);
+        G.lds = __builtin_amdgcn_readlane((int)Gl.lds, i) != 0;
+        fwd_box<T, LT, ALIGNED, kDispNone>(J, G, SL, s_lds, lds_cells, Q0);
+    }
 }
 
 template <typename T, bool ALIGNED, int DISP>
@@ -416,7 +442,9 @@ int32_t footprint_cells_bound(const FwdJob &J, const Tiling &TL)
 // cells: the whole tile when its footprint bound fits; otherwise the sub-box
 // of the tile with the most voxels (at least 2^10, or the tile's own count if
 // smaller; z extent >= 4) whose bound fits, fewest cells per voxel among
-// equals; the whole tile (direct gathers) when none fits.
+// equals; the whole tile (direct gathers) when none fits.  As tiles hold at
+// most 2^14 voxels, a tile has at most 16 sub-tiles (the kernels read one
+// sub-tile's geometry per lane of a wave).
 Tiling choose_subtile(const FwdJob &J, const Tiling &TL, int32_t lds_cells)
 {
     if (J.disp || J.ctrl || lds_cells <= 0 || footprint_cells_bound(J, TL) <= lds_cells)
