@@ -459,7 +459,7 @@ extern "C" ctaug_status ctaug_warp_labels(const ctaug_vol *lbl_in, const float M
     std::memset(&J, 0, sizeof J);
     J.lbl = static_cast<const int8_t *>(lbl_in->data);
     J.lout = static_cast<int8_t *>(lbl_out->data);
-    J.dtype = CTAUG_I8;
+    J.dtype = kI8;                     // labels only: no image
     J.nx = (int32_t)lbl_in->dim[0];
     J.ny = (int32_t)lbl_in->dim[1];
     J.nz = (int32_t)lbl_in->dim[2];

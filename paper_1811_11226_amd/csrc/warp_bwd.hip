@@ -167,6 +167,13 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
                       kSplineBwdCells,
                   "the tile's contraction scratch fits the footprint reservation");
     const int t = threadIdx.x;
+    // controls of the tile's window per axis (at most NW): contractions stop
+    // there, as every weight beyond is zero and no later stage reads beyond
+    const int ixl = bs_index(x0, B.inv_hx, B.gx), iyl = bs_index(y0, B.inv_hy, B.gy),
+              izl = bs_index(z0, B.inv_hz, B.gz);
+    const int ncx = bs_index(x1, B.inv_hx, B.gx) - ixl + 4,
+              ncy = bs_index(y1, B.inv_hy, B.gy) - iyl + 4,
+              ncz = bs_index(z1, B.inv_hz, B.gz) - izl + 4;
     if (t < 16 * NW)
         spline_weight_entry(t, z0, z1, B.inv_hz, B.gz, Zw);
     else if (t < 24 * NW)
@@ -176,7 +183,7 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
     __syncthreads();
     // z: the 4 lanes of a row hold its 16 voxels; butterfly sum over them
 #pragma unroll 1
-    for (int c = 0; c < NW; ++c) {
+    for (int c = 0; c < ncz; ++c) {
         const float *zc = Zw + zr * NW + c;    // voxel k of the run sits at z offset zr + 4k
         const float w0 = zc[0], w1 = zc[4 * NW], w2 = zc[8 * NW], w3 = zc[12 * NW];
 #pragma unroll
@@ -191,7 +198,7 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
         }
     }
     __syncthreads();
-    if (t < 8 * 3 * NW) {                      // (x, i, c) -> H[x][i][b][c] for every b
+    if (t < 8 * 3 * NW && (t & (NW - 1)) < ncz) {   // (x, i, c) -> H[x][i][b][c], b < ncy
         const int xr = t / (3 * NW), ic = t - xr * 3 * NW;
         const int i = ic / NW, c = ic - i * NW;
         float wv[8];
@@ -199,7 +206,7 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
         for (int yr = 0; yr < 8; ++yr)
             wv[yr] = W[((xr * 8 + yr) * 3 + i) * NW + c];
 #pragma unroll 1
-        for (int b = 0; b < NW; ++b) {
+        for (int b = 0; b < ncy; ++b) {
             float h = 0.0f;
 #pragma unroll
             for (int yr = 0; yr < 8; ++yr)
@@ -208,14 +215,15 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
         }
     }
     __syncthreads();
-    if (t < 3 * NW * NW) {                     // (i, b, c) -> R[i][a][b][c] for every a
+    if (t < 3 * NW * NW && (t & (NW - 1)) < ncz && ((t >> 3) & (NW - 1)) < ncy) {
+        // (i, b, c) -> R[i][a][b][c], a < ncx
         const int i = t / (NW * NW), bc = t - i * NW * NW;
         float hv[8];
 #pragma unroll
         for (int xr = 0; xr < 8; ++xr)
             hv[xr] = H[(xr * 3 + i) * NW * NW + bc];
 #pragma unroll 1
-        for (int a = 0; a < NW; ++a) {
+        for (int a = 0; a < ncx; ++a) {
             float r = 0.0f;
 #pragma unroll
             for (int xr = 0; xr < 8; ++xr)
@@ -224,11 +232,6 @@ __device__ __forceinline__ void ctrl_adjoint_tile(const BsplineGeom &B, int x0, 
         }
     }
     __syncthreads();
-    const int ixl = bs_index(x0, B.inv_hx, B.gx), iyl = bs_index(y0, B.inv_hy, B.gy),
-              izl = bs_index(z0, B.inv_hz, B.gz);
-    const int ncx = bs_index(x1, B.inv_hx, B.gx) - ixl + 4,
-              ncy = bs_index(y1, B.inv_hy, B.gy) - iyl + 4,
-              ncz = bs_index(z1, B.inv_hz, B.gz) - izl + 4;
     for (int e = t; e < 3 * NW * NW * NW; e += kThreads) {
         const int c = e & (NW - 1), b = (e >> 3) & (NW - 1), a = (e >> 6) & (NW - 1), i = e >> 9;
         if (a < ncx && b < ncy && c < ncz)
