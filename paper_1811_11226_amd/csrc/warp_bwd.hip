@@ -486,11 +486,13 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
     if (lds) {
         if (g_img) {
             // the tile's largest |g| (the waves' maxima, written before the
-            // barrier that ended the corner reads)
+            // barrier that ended the corner reads); every wave reads it before
+            // any wave goes on to the next tile, which writes s_gmax again
             float gm = s_gmax[0];
 #pragma unroll
             for (int w = 1; w < kThreads / 64; ++w)
                 gm = fmaxf(gm, s_gmax[w]);
+            __syncthreads();
             // x-planes of 64-bit accumulators that fit the footprint reservation
             const int planes = (lds_cells >> 1) / sxy;
             const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;

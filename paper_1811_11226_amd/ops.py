@@ -287,6 +287,7 @@ def make_bwd_job(img, M, grad_out, grad_img=None, grad_M=None, fill=-1000.0, pho
         ph = _lib.Photo()
         ph.flags = CTAUG_PHOTO_NONE
     j.photo = ph
+    j._keep = (img, grad_out, grad_img, grad_M)   # the job holds raw device pointers
     return j
 
 
@@ -416,7 +417,16 @@ def make_job(img, M, out, lbl=None, lbl_out=None, fill=-1000.0, label_fill=0, ph
         ph.flags = CTAUG_PHOTO_NONE
         ph.gain, ph.gamma, ph.win_hi = 1.0, 1.0, 1.0
     j.photo = ph
+    j._keep = (img, out, lbl, lbl_out, ctrl)   # the job holds raw device pointers
     return j
+
+
+def _job_array(jobs):
+    # ctypes copies the structs into the array; the tensors they point to stay
+    # referenced from the array
+    arr = (_lib.Job * len(jobs))(*jobs)
+    arr._keep = [getattr(j, "_keep", None) for j in jobs]
+    return arr
 
 
 class BatchPlan:
@@ -425,7 +435,7 @@ class BatchPlan:
 
     def __init__(self, jobs, tile=None, wg_per_cu=0, lds_cells=0, lds_format=0):
         self._L = _lib.load()
-        arr = (_lib.Job * len(jobs))(*jobs)
+        arr = jobs if isinstance(jobs, ctypes.Array) else _job_array(jobs)
         tune = None
         if tile is not None:
             tune = _lib.Tuning()
@@ -438,11 +448,12 @@ class BatchPlan:
                    "ctaug_batch_plan_create")
         self._h = h
         self.n = len(jobs)
+        self._jobs = arr                # the tensors the device table points to stay alive
 
     @staticmethod
     def job_array(jobs):
         """The ctypes array of a list of jobs, reusable across update() calls."""
-        return (_lib.Job * len(jobs))(*jobs)
+        return _job_array(jobs)
 
     def update(self, jobs):
         """New job contents: a list of jobs or an array from job_array()."""
@@ -450,6 +461,7 @@ class BatchPlan:
         if len(arr) != self.n:
             raise ValueError(f"expected {self.n} jobs, got {len(arr)}")
         _lib.check(self._L.ctaug_batch_plan_update(self._h, arr), "ctaug_batch_plan_update")
+        self._jobs = arr                # the tensors the device table points to stay alive
 
     def prepare(self, jobs):
         """Descriptors of `jobs` validated and built once, for update_prepared()."""
@@ -461,6 +473,7 @@ class BatchPlan:
     def update_prepared(self, prepared):
         _lib.check(self._L.ctaug_batch_plan_update_prepared(self._h, prepared._h),
                    "ctaug_batch_plan_update_prepared")
+        self._jobs = prepared._arr
 
     def launch(self):
         _lib.check(self._L.ctaug_batch_plan_launch(self._h, _stream()), "ctaug_batch_plan_launch")

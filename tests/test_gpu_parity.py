@@ -44,7 +44,8 @@ def assert_grad(got, ref, what=""):
     nref = np.linalg.norm(ref)
     assert np.linalg.norm(got - ref) <= 1e-4 * max(nref, 1e-30), \
         f"{what}: normwise {np.linalg.norm(got - ref) / max(nref, 1e-30):.3e}"
-    floor = 1e-2 * np.abs(ref).max() if ref.size else 0.0
+    # (an all-zero reference takes the normwise bar above: got must be zero)
+    floor = max(1e-2 * np.abs(ref).max() if ref.size else 0.0, np.finfo(np.float64).tiny)
     err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
     assert err.size == 0 or err.max() <= 1e-4, f"{what}: elementwise {err.max():.3e}"
 
@@ -934,6 +935,36 @@ def test_batch_launch_shapes_bit_identical(tile, wg, lds, fmt):
     plan.close()
 
 
+@pytest.mark.parametrize("tiles", [(1,), (31, 32), (33, 32), (255, 256), (257, 256),
+                                   (64, 64, 64, 64, 64, 64, 64, 65)])
+@pytest.mark.parametrize("wg", [0, 1])
+def test_batch_tile_counts_around_xcd_chunks(tiles, wg):
+    """Batches whose tile totals fall just below and above the XCD chunk (64
+    tiles) and a whole round of chunks (512 tiles), one workgroup per tile
+    and persistent: every tile is warped exactly once, bit for bit as single
+    calls."""
+    rng = np.random.default_rng(sum(tiles) + wg)
+    items = []
+    for k, n in enumerate(tiles):
+        out_dim = (4, 4, 4 * n)                # n tiles of 4 x 4 x 4
+        in_dim = (9, 7, 4 * n + 3)
+        img, lbl = phantom_pair(in_dim, seed=600 + k)
+        prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+        _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+        ph = draw_photo(rng, AugmentRanges(), seed=12, volume_id=k)
+        items.append((_t(img), _t(lbl), M, ph, out_dim,
+                      torch.full(out_dim, float("nan"), dtype=torch.float32, device=DEV),
+                      torch.full(out_dim, 77, dtype=torch.int8, device=DEV)))
+    jobs = [ctaug.make_job(im, M, o, lb, lo, photo=ph) for im, lb, M, ph, od, o, lo in items]
+    plan = ctaug.BatchPlan(jobs, tile=(4, 4, 4), wg_per_cu=wg)
+    plan.launch()
+    for im, lb, M, ph, od, o, lo in items:
+        ref, lref = ctaug.warp_affine(im, M, lbl=lb, photo=ph, out_dim=od)
+        assert np.array_equal(_np(o).view(np.uint32), _np(ref).view(np.uint32))
+        assert torch.equal(lo, lref)
+    plan.close()
+
+
 def test_batch_graph_replay_with_updates():
     T = _batch_jobs(n=3)
     jobs = [ctaug.make_job(img, M, out, lbl, lout, fill=j.fill, photo=j.photo)
@@ -1175,6 +1206,38 @@ def test_prepared_updates_equal_updates_and_go_stale_on_retuning():
         p.close()
     plan.close()
     ctaug.autotune_cache_clear()
+
+
+@pytest.mark.parametrize("tiles", [(1,), (63,), (31, 33), (256, 257), (600, 600)])
+def test_batched_backward_tile_counts_around_xcd_chunks(tiles):
+    """The batched adjoint over tile totals around the XCD chunk (64 tiles),
+    a round of chunks (512) and more tiles than resident workgroups (1200):
+    grad_img and grad_M of every job against single calls and the oracle.  The
+    input tensors are made inline: the job keeps them alive."""
+    rng = np.random.default_rng(sum(tiles))
+    items = []
+    for k, n in enumerate(tiles):
+        out_dim = (8, 8, 16 * n)               # n adjoint tiles of 8 x 8 x 16
+        in_dim = (12, 11, 16 * n + 5)
+        img, _ = phantom_pair(in_dim, seed=700 + k)
+        img = img.astype(np.float32)
+        prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+        _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+        g = rng.standard_normal(out_dim).astype(np.float32)
+        items.append((img, M, g))
+    gis = [torch.zeros(it[0].shape, dtype=torch.float32, device=DEV) for it in items]
+    gMs = [torch.empty(12, dtype=torch.float64, device=DEV) for _ in items]
+    jobs = [ctaug.ops.make_bwd_job(_t(img), M, _t(g), grad_img=gi, grad_M=gM)
+            for (img, M, g), gi, gM in zip(items, gis, gMs)]
+    ctaug.ops.warp_affine_backward_batch(jobs)
+    for k, (img, M, g) in enumerate(items):
+        s_img, s_M = ctaug.warp_affine_backward(_t(img), M, _t(g))
+        assert_grad(_np(gis[k]), _np(s_img).astype(np.float64), f"job {k} g_img vs single")
+        np.testing.assert_allclose(_np(gMs[k]), _np(s_M), rtol=1e-12,
+                                   atol=1e-12 * np.abs(_np(s_M)).max())
+        r_img, r_M, _ = oracle.warp_backward(img, M, g)
+        assert_grad(_np(gis[k]), r_img, f"job {k} g_img vs oracle")
+        assert_grad(_np(gMs[k]), r_M, f"job {k} g_M vs oracle")
 
 
 @pytest.mark.parametrize("dtype,n", [(np.float32, 10), (np.int16, 3)])
