@@ -404,6 +404,32 @@ def run_c2(dev, stream, reps):
             "alg_GBs": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
+def run_labels_back(dev, stream, reps):
+    """Nearest-neighbour resampling of a predicted label map back to the
+    original grid (labels only, no image): 160x160x100 int8 -> 512x512x320."""
+    import numpy as np
+    import torch
+
+    import paper_1811_11226_amd as ctaug
+    from synth import phantom_pair
+    pred_dim, orig_dim = (160, 160, 100), (512, 512, 320)
+    _, lbl = phantom_pair(pred_dim, seed=20181129)
+    lin = torch.from_numpy(lbl).to(dev)
+    M = np.zeros(12, np.float32)
+    for i in range(3):                  # voxel p of the original grid reads (p + 1/2) r - 1/2
+        r = pred_dim[i] / orig_dim[i]
+        M[4 * i + i] = r
+        M[4 * i + 3] = 0.5 * r - 0.5
+    lout = torch.empty(orig_dim, dtype=torch.int8, device=dev)
+    ms = time_loop(lambda: ctaug.warp_labels(lin, M, label_fill=0, lbl_out=lout), reps, stream)
+    nv = lout.numel()
+    alg = nv + lin.numel()              # every output byte written, every input byte read
+    return {"workload": "labels only: 160x160x100 int8 prediction resampled back to "
+                        "512x512x320 by nearest neighbour",
+            "ms": round(ms, 4), "gvoxel_s": round(nv / ms / 1e6, 2),
+            "alg_GBs": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
 def run_c4(dev, stream, reps):
     import torch
 
@@ -863,6 +889,8 @@ def main():
         sec = {}
         log("secondary: 512x512x320")
         sec["full_res_512x512x320"] = run_c2(dev, stream, reps=10)
+        log("secondary: labels resampled back")
+        sec["labels_back_512x512x320"] = run_labels_back(dev, stream, reps=20)
         log("secondary: 8 x 128^3 fwd / fwd+bwd")
         sec["diff_affine_8x128"] = run_c4(dev, stream, reps=10)
         log("secondary: 4 x 256^3 nonrigid fwd / fwd+bwd")

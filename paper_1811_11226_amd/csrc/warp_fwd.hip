@@ -515,16 +515,17 @@ static_assert(2 * kDispLdsCells >= kSplineTileLdsFloats * (int32_t)sizeof(float)
 // Labels alone: one thread per run of 4 output voxels along z (one packed
 // 4-byte store with kFlagVec), the coordinate and the nearest-neighbour gather
 // of the fused warps (row_base, coord, label_checked), so the labels equal
-// theirs bit for bit.  Runs are numbered z-fastest: run r covers z = 4 (r mod
-// runs_z) .. + 3 of row r / runs_z = x * Yo + y.
-__global__ __launch_bounds__(kThreads) void k_warp_labels(FwdJob J, int32_t runs_z, int64_t nruns)
+// theirs bit for bit.  Block row blockIdx.y is the x-slab x = x0 + blockIdx.y;
+// within it run r covers z = 4 (r mod runs_z) .. + 3 of y = r / runs_z.
+__global__ __launch_bounds__(kThreads) void k_warp_labels(FwdJob J, int32_t runs_z, int32_t x0)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= nruns)
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= J.oy * runs_z)
         return;
-    const int32_t row = (int32_t)(r / runs_z);
-    const int z = 4 * (int)(r - (int64_t)row * runs_z);
-    const int x = row / J.oy, y = row - x * J.oy;
+    const int x = x0 + (int)blockIdx.y;
+    const int y = r / runs_z;
+    const int z = 4 * (r - y * runs_z);
+    const int32_t row = x * J.oy + y;
     Src S;
     S.lbl = make_rsrc(J.lbl, (uint32_t)J.in_extent);
     S.img = S.lbl;                     // not read
@@ -565,12 +566,14 @@ __global__ __launch_bounds__(kThreads) void k_warp_labels(FwdJob J, int32_t runs
 hipError_t launch_warp_labels(const FwdJob &J, hipStream_t s)
 {
     const int32_t runs_z = (J.oz + 3) >> 2;
-    const int64_t nruns = (int64_t)J.ox * J.oy * runs_z;
-    if (nruns == 0)
+    const int64_t slab = (int64_t)J.oy * runs_z;     // runs per x-slab (< 2^31)
+    if (slab == 0 || J.ox == 0)
         return hipSuccess;
-    const int64_t blocks = (nruns + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_warp_labels, dim3((unsigned)blocks), dim3(kThreads), 0, s, J, runs_z,
-                       nruns);
+    const unsigned bx = (unsigned)((slab + kThreads - 1) / kThreads);
+    for (int32_t x0 = 0; x0 < J.ox; x0 += 65535) {   // grid y: at most 65535 slabs a launch
+        const unsigned nx = (unsigned)std::min<int32_t>(65535, J.ox - x0);
+        hipLaunchKernelGGL(k_warp_labels, dim3(bx, nx), dim3(kThreads), 0, s, J, runs_z, x0);
+    }
     return hipGetLastError();
 }
 
