@@ -98,3 +98,14 @@ def test_labels_only_edge_cases():
                                               (2, 2, 2), 1))
     empty = ctaug.warp_labels(_t(lbl), M, out_dim=(3, 0, 4))
     assert empty.numel() == 0
+
+
+def test_labels_only_more_x_slabs_than_one_launch_row():
+    """An output with more x slabs (70000) than one launch's second grid axis
+    holds (65535): the slabs past it go to a second launch."""
+    rng = np.random.default_rng(9)
+    lbl = rng.integers(-5, 6, size=(1200, 2, 5)).astype(np.int8)
+    M = np.array([1200 / 70000, 0, 0, 0.1, 0, 1, 0, 0, 0, 0, 1.1, -0.2], np.float32)
+    out_dim = (70000, 1, 4)
+    got = _np(ctaug.warp_labels(_t(lbl), M, out_dim=out_dim, label_fill=3))
+    assert np.array_equal(got, _oracle_labels(lbl, M, out_dim, 3))
