@@ -257,10 +257,15 @@ size_t ctaug_warp_backward_workspace(const int64_t out_dim[3]);
  *   grad_M[i][j] = sum_p g(p) dV/dq_i(p) [x,y,z,1]_j   (overwritten)
  * dV/dq is the derivative of the interpolant on the cell floor(q) (fill
  * corners included, i.e. the right derivative at integer q); samples outside
- * (-1, n) contribute nothing.  The sums of grad_img are exact within each
- * output tile (64-bit fixed point) and tiles meet in FP32 atomics; a tile
- * with a non-finite g adds per corner in FP32 (NaN and infinities reach
- * every in-volume corner of the voxel's cell, as 0 * NaN = NaN).
+ * (-1, n) contribute nothing.  grad_img is summed per output tile in fixed
+ * point scaled by the tile's largest |g| (gmax), independent of the order of
+ * the additions, and tiles meet in FP32 atomics.  Where the map bounds how
+ * many of a tile's samples share an input cell by 2^b, b <= 7 (the usual
+ * augmentation range; not for strong upsampling or a near-singular A), the
+ * tile sums are 32-bit: each contribution is rounded to within 2^(b - 30)
+ * gmax.  Otherwise they are 64-bit and exact to 2^-51 gmax.  A tile with a
+ * non-finite g adds per corner in FP32 (NaN and infinities reach every
+ * in-volume corner of the voxel's cell, as 0 * NaN = NaN).
  * img_in: device F32/I16 (may be strided); photo: host, WINDOW not allowed
  * (EINVAL); grad_out: device F32 with the output dims; grad_img: device F32
  * with img_in's dims (dense), or NULL; grad_M: device double[12], or NULL.
@@ -297,7 +302,8 @@ ctaug_status ctaug_warp_affine_backward_noalloc(const ctaug_vol *img_in, const f
  * ctaug_warp_affine_backward for one volume: grad_img.data == NULL means no
  * image gradient, grad_M == NULL no parameter gradient, photo.flags with
  * CTAUG_PHOTO_NONE no photometric chain.  Results: as one call per job;
- * grad_img sums are exact within an output tile and meet in FP32 atomics,
+ * grad_img tile sums are fixed point and meet in FP32 atomics (32-bit sums
+ * when every job of the launch has the single call's bound, else 64-bit),
  * grad_M is reduced in FP64 in a fixed order over the launch's workgroups
  * (deterministic for a given device and batch; its rounding may differ from
  * the single call's, which reduces over a different set of rows).  Every

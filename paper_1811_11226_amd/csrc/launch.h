@@ -68,6 +68,7 @@ constexpr int32_t kBwdBatchMax = 8;    // jobs per launch (the table travels in 
 struct BwdBatch {
     BwdJob jobs[kBwdBatchMax];
     int32_t prefix[kBwdBatchMax + 1];
+    int32_t fix_bits[kBwdBatchMax];    // per job: 32-bit fixed-point exponent, or -1
     int32_t njobs;
 };
 hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials, hipStream_t s);

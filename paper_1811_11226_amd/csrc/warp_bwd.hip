@@ -6,9 +6,11 @@
 // recomputed; the eight corner values
 // (staged in LDS, fill substituted outside the volume) give the derivative of
 // the trilinear interpolant on that cell, dV/dq.  Then
-//   grad_img[c] += w_c * g          summed per tile in 64-bit fixed point in
-//                                   LDS (integer atomics, order-independent),
-//                                   then one global FP32 atomic per touched
+//   grad_img[c] += w_c * g          summed per tile in fixed point in LDS
+//                                   (integer atomics, order-independent; 32
+//                                   bits in one pass where the host bounds a
+//                                   cell's samples, else 64 bits in x-plane
+//                                   passes), then one global FP32 atomic per touched
 //                                   cell; tiles whose footprint exceeds the
 //                                   reservation, or with non-finite g, add
 //                                   per corner with global FP32 atomics
@@ -115,6 +117,20 @@ __device__ __forceinline__ long long to_fixed(float v, double S)
     constexpr double kMagic = 0x1.8p52;
     const double d = __builtin_fma((double)v, S, kMagic);
     return __double_as_longlong(d) - __double_as_longlong(kMagic);
+}
+
+// The 32-bit variant for affine jobs, one pass over the whole footprint (the
+// accumulators take the cells the staged image took).  The host bounds how
+// many of a tile's samples can have one input cell among their corners: at
+// most 2^b (fixed32_bits).  Each contribution is scaled by 2^sc, sc = 30 - b
+// - e (v_ldexp, exact), and rounded to the nearest integer: |v 2^sc| <
+// 2^(30 - b), so a cell's sum of at most 2^b of them stays within 2^30.  The
+// unit 2^-sc is at most 2^(b - 29) gmax, so for b <= kFixed32MaxBits the
+// rounding stays within 2^-23 gmax, the order of the FP32 product's own.
+constexpr int kFixed32MaxBits = 7;
+__device__ __forceinline__ int to_fixed32(float v, int sc)
+{
+    return (int)__builtin_rintf(__builtin_ldexpf(v, sc));
 }
 
 // Spline weight matrix of one tile axis: Wt[p][c] = B_{c - (i(p) - i(p0))}(t(p))
@@ -269,13 +285,14 @@ __device__ __forceinline__ void write_partial_row(const double (&acc)[12],
 // adjoint (fixed-point tile sums, flushed with FP32 atomics), the
 // displacement gradient and the control-grid contraction.  Uniform over the
 // workgroup; ends with every LDS read and write of the tile done.
-template <typename T, int DISP>
+template <typename T, int DISP, bool NARROW>
 __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                                          gconst<float> *disp, int32_t nvox, bool empty_in,
                                          bool want_ctrl, bool need_dv, const float *__restrict__ g,
                                          float *__restrict__ g_img, float *__restrict__ g_disp,
-                                         float *s_ctrl, int32_t lds_cells, int zr, int yr, int xr,
-                                         double (&acc)[12], int (*s_red)[6], float *s_gmax)
+                                         float *s_ctrl, int32_t lds_cells, int fix_bits, int zr,
+                                         int yr, int xr, double (&acc)[12], int (*s_red)[6],
+                                         float *s_gmax)
 {
     const Tiling TL = kBwdTiling;
     const int tz = t % J.tiles_z, rest = t / J.tiles_z;
@@ -496,7 +513,51 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
             // x-planes of 64-bit accumulators that fit the footprint reservation
             const int planes = (lds_cells >> 1) / sxy;
             const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
-            if (gm > 0.0f && gm <= 3.40282347e38f && planes > 0) {
+            if (NARROW && gm >= 0x1p-96f && gm <= 3.40282347e38f) {
+                // one pass, 32-bit accumulators (gmax >= 2^-96 keeps every
+                // scaled value and every flushed sum in the normal range)
+                const int sc = 30 - fix_bits - (ilogbf(gm) + 1);
+                int *s_acc = reinterpret_cast<int *>(s_cells);
+                const int n = G.e[0] * sxy;                      // a multiple of 4
+                for (int c = 4 * threadIdx.x; c < n; c += 4 * kThreads)
+                    *reinterpret_cast<f32x4 *>(s_acc + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (!live[k])
+                        continue;
+                    const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
+                    const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
+                    const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int bb = 0; bb < 2; ++bb) {
+                            const float wxy = wx[a] * wy[bb];
+                            int *row = s_acc + base[k] + a * sxy + bb * pitch;
+                            atomicAdd(row, to_fixed32(wxy * gz0, sc));
+                            atomicAdd(row + 1, to_fixed32(wxy * gz1, sc));
+                        }
+                    __builtin_amdgcn_sched_barrier(0);       // one voxel at a time
+                }
+                __syncthreads();
+                // flush: one global atomic per touched in-volume footprint cell
+                for (int c = threadIdx.x; c < n; c += kThreads) {
+                    const int v = s_acc[c];
+                    if (v == 0)
+                        continue;
+                    const int row = div_small(c, pitch, rcp_pitch);
+                    const int cz = c - row * pitch;
+                    const int cx = div_small(row, ey, rcp_ey);
+                    const int cy = row - cx * ey;
+                    const int gx = G.lo[0] + cx, gy = G.lo[1] + cy, gz = G.lo[2] + cz;
+                    if (cz < G.e[2] && (unsigned)gx < (unsigned)J.nx &&
+                        (unsigned)gy < (unsigned)J.ny && (unsigned)gz < (unsigned)J.nz)
+                        unsafeAtomicAdd(g_img + (gx * J.ny + gy) * J.nz + gz,
+                                        __builtin_ldexpf((float)v, -sc));
+                }
+                __syncthreads();       // LDS is reused next
+            } else if (!NARROW && gm > 0.0f && gm <= 3.40282347e38f && planes > 0) {
                 const int e = ilogbf(gm) + 1;          // gm < 2^e
                 const double S = ldexp(1.0, 50 - e);
                 const double rS = ldexp(1.0, e - 50);
@@ -551,8 +612,9 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                     __syncthreads();   // LDS is reused next
                 }
             } else if (gm != 0.0f) {
-                // non-finite gradients (or a footprint too large for one
-                // x-plane of accumulators): FP32 global atomics per corner
+                // non-finite gradients, a footprint too large for one x-plane
+                // of 64-bit accumulators, or a 32-bit tile with gmax < 2^-96:
+                // FP32 global atomics per corner
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (!live[k])
@@ -582,15 +644,18 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
 // Register budgets follow the LDS: a displacement takes the whole 48 KB
 // reservation (3 workgroups per CU), so at most 168 VGPRs (3 waves per SIMD);
 // an affine job's footprint bound usually keeps a workgroup within 40 KB
-// (4 per CU), so at most 128 VGPRs, a few of them spilled.
-template <typename T, int DISP>
+// (4 per CU), so at most 128 VGPRs, a few of them spilled.  NARROW (affine
+// jobs with a bound fix_bits >= 0) takes the 32-bit image adjoint: a kernel
+// of its own, as register allocation over both fixed-point paths spills.
+template <typename T, int DISP, bool NARROW>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     DISP == kDispNone ? 4 : 3))) void k_warp_bwd(FwdJob J, const float *__restrict__ g,
                                                        float *__restrict__ g_img,
                                                        float *__restrict__ g_disp,
                                                        double *__restrict__ partials,
                                                        double *__restrict__ ctrl_part,
-                                                       int32_t ntiles, int32_t lds_cells)
+                                                       int32_t ntiles, int32_t lds_cells,
+                                                       int32_t fix_bits)
 {
     const int b = blockIdx.x;
     const int per_xcd_wg = gridDim.x >> 3;
@@ -631,8 +696,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         const int t = xcd_tile(b & 7, slots.slot());
         if (t >= ntiles)
             break;
-        bwd_tile<T, DISP>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, g, g_img, g_disp,
-                          s_ctrl, lds_cells, zr, yr, xr, acc, s_red, s_gmax);
+        bwd_tile<T, DISP, NARROW>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, g, g_img, g_disp,
+                          s_ctrl, lds_cells, fix_bits, zr, yr, xr, acc, s_red, s_gmax);
     }
 
     if (want_ctrl)                         // the last tile ended with a barrier
@@ -653,7 +718,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 // increasing order.  The
 // workgroup's FP64 parameter sums of job j go to partials row
 // j * gridDim.x + b (rows of jobs it never meets stay as zeroed before).
-template <typename T>
+template <typename T, bool NARROW>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_warp_bwd_batch(const BwdBatch B,
                                                              double *__restrict__ partials,
                                                              int32_t lds_cells)
@@ -691,9 +756,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const BwdJob &BJ = B.jobs[j];
         const Src src = make_src<T>(BJ.J);
         const bool empty_in = BJ.J.nx == 0 || BJ.J.ny == 0 || BJ.J.nz == 0;
-        bwd_tile<T, kDispNone>(BJ.J, t - B.prefix[j], src, nullptr, BJ.J.ox * BJ.J.oy * BJ.J.oz,
+        bwd_tile<T, kDispNone, NARROW>(BJ.J, t - B.prefix[j], src, nullptr, BJ.J.ox * BJ.J.oy * BJ.J.oz,
                                empty_in, false, BJ.g_M != nullptr, BJ.g, BJ.g_img, nullptr,
-                               nullptr, lds_cells, zr, yr, xr, acc, s_red, s_gmax);
+                               nullptr, lds_cells, B.fix_bits[j], zr, yr, xr, acc, s_red,
+                               s_gmax);
     }
     if (jcur >= 0 && B.jobs[jcur].g_M)
         write_partial_row(acc, red, partials + ((int64_t)jcur * gridDim.x + b) * 12);
@@ -861,6 +927,45 @@ bool bwd_ctrl_fused(const BsplineGeom &B)
            max_window(B.oy, kBwdTiling.ly, B.inv_hy, B.gy) <= kSplineWindow;
 }
 
+// Exponent b of the 32-bit fixed-point image adjoint of an affine job (see
+// to_fixed32), or -1 for the 64-bit one.  Sample p reaches input cell c when
+// q(p) = A p + t lies in [c - 1, c + 1) per axis, widened by the bound delta
+// on q's FP32 rounding; those p lie in A^-1 of that cube, whose extent along
+// output axis i is w_i = (2 + 2 delta) sum_j |A^-1_ij|, which holds at most
+// floor(w_i) + 1 integer values of p_i, and the tile at most its extent.  A strongly shrinking or
+// near-singular map exceeds kFixed32MaxBits and keeps 64-bit sums.
+static int32_t fixed32_bits(const FwdJob &J)
+{
+    double a[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            a[i][j] = (double)J.M[4 * i + j];
+    double c[3][3];                    // cofactors
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            c[i][j] = a[i1][j1] * a[i2][j2] - a[i1][j2] * a[i2][j1];
+        }
+    const double det = a[0][0] * c[0][0] + a[0][1] * c[0][1] + a[0][2] * c[0][2];
+    if (!std::isfinite(det) || det == 0.0)
+        return -1;
+    const double slack = std::max({(double)J.delta[0], (double)J.delta[1], (double)J.delta[2]});
+    const int ext[3] = {1 << kBwdTiling.lx, 1 << kBwdTiling.ly, 1 << kBwdTiling.lz};
+    int64_t K = 1;
+    for (int i = 0; i < 3; ++i) {      // row i of A^-1 = column i of the cofactors / det
+        const double w =
+            (2.0 + 2.0 * slack) *
+            (std::fabs(c[0][i]) + std::fabs(c[1][i]) + std::fabs(c[2][i])) / std::fabs(det);
+        K *= (std::isfinite(w) && w < (double)ext[i])
+                 ? std::min<int64_t>(ext[i], (int64_t)std::floor(w) + 1)
+                 : ext[i];
+    }
+    int b = 0;
+    while (((int64_t)1 << b) < K)
+        ++b;
+    return b <= kFixed32MaxBits ? b : -1;
+}
+
 // Workgroups the device keeps resident for kernel fn with lds bytes of dynamic
 // LDS (occupancy x compute units), cached per device, kernel and LDS size.
 static int resident_groups(const void *fn, size_t lds)
@@ -907,16 +1012,27 @@ static int launch_bwd_t(const FwdJob &J, int64_t ntiles, size_t lds, hipStream_t
                         const float *g, float *g_img, float *g_disp, double *part,
                         double *ctrl_part, int32_t cells)
 {
-    const void *fn = J.dtype == kI16 ? reinterpret_cast<const void *>(&k_warp_bwd<int16_t, DISP>)
-                                     : reinterpret_cast<const void *>(&k_warp_bwd<float, DISP>);
-    const int grid = bwd_launch_grid(fn, lds, ntiles);
+    const int32_t fix_bits = DISP == kDispNone ? fixed32_bits(J) : -1;
     const int nt = (int)ntiles;
+    int grid = 0;
+    auto launch = [&](auto kern) {
+        grid = bwd_launch_grid(reinterpret_cast<const void *>(kern), lds, ntiles);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, J, g, g_img, g_disp, part,
+                           ctrl_part, nt, cells, fix_bits);
+    };
+    if constexpr (DISP == kDispNone) {
+        if (fix_bits >= 0) {
+            if (J.dtype == kI16)
+                launch(&k_warp_bwd<int16_t, DISP, true>);
+            else
+                launch(&k_warp_bwd<float, DISP, true>);
+            return grid;
+        }
+    }
     if (J.dtype == kI16)
-        hipLaunchKernelGGL((k_warp_bwd<int16_t, DISP>), dim3(grid), dim3(kThreads), lds, s, J, g,
-                           g_img, g_disp, part, ctrl_part, nt, cells);
+        launch(&k_warp_bwd<int16_t, DISP, false>);
     else
-        hipLaunchKernelGGL((k_warp_bwd<float, DISP>), dim3(grid), dim3(kThreads), lds, s, J, g,
-                           g_img, g_disp, part, ctrl_part, nt, cells);
+        launch(&k_warp_bwd<float, DISP, false>);
     return grid;
 }
 
@@ -993,6 +1109,7 @@ hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials
             J.tiles_y = (J.oy + 7) >> 3;
             J.tiles_z = (J.oz + 15) >> 4;
             B.prefix[i] = (int32_t)total;
+            B.fix_bits[i] = fixed32_bits(J);
             total += (int64_t)J.tiles_x * J.tiles_y * J.tiles_z;
             if (J.nx > 0 && J.ny > 0 && J.nz > 0 && J.ox > 0 && J.oy > 0 && J.oz > 0)
                 cells = std::max(cells, std::min(footprint_cells_bound(J, kBwdTiling), kBwdLdsCells));
@@ -1002,9 +1119,15 @@ hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials
         double *part = partials + (int64_t)c0 * kBwdMaxRows * 12;
         const bool i16 = B.jobs[0].J.dtype == kI16;
         const size_t lds = (size_t)cells * sizeof(float);
-        const void *fn = i16 ? reinterpret_cast<const void *>(&k_warp_bwd_batch<int16_t>)
-                             : reinterpret_cast<const void *>(&k_warp_bwd_batch<float>);
-        const int grid = total > 0 ? bwd_launch_grid(fn, lds, total) : 8;
+        bool narrow = true;            // the 32-bit image adjoint when every job has a bound
+        for (int i = 0; i < B.njobs; ++i)
+            narrow = narrow && B.fix_bits[i] >= 0;
+        using BatchKernel = void (*)(const BwdBatch, double *, int32_t);
+        const BatchKernel kern =
+            i16 ? (narrow ? &k_warp_bwd_batch<int16_t, true> : &k_warp_bwd_batch<int16_t, false>)
+                : (narrow ? &k_warp_bwd_batch<float, true> : &k_warp_bwd_batch<float, false>);
+        const int grid =
+            total > 0 ? bwd_launch_grid(reinterpret_cast<const void *>(kern), lds, total) : 8;
         if (any_M) {
             const int64_t nz = (int64_t)B.njobs * grid * 12;
             hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((nz + kThreads - 1) / kThreads)),
@@ -1014,12 +1137,7 @@ hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials
                 return e;
         }
         if (total > 0) {
-            if (i16)
-                hipLaunchKernelGGL(k_warp_bwd_batch<int16_t>, dim3(grid), dim3(kThreads), lds, s, B,
-                                   part, cells);
-            else
-                hipLaunchKernelGGL(k_warp_bwd_batch<float>, dim3(grid), dim3(kThreads), lds, s, B,
-                                   part, cells);
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, B, part, cells);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;

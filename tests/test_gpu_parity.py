@@ -538,6 +538,7 @@ def test_affine_backward_gradient_magnitudes(gscale, outliers):
     ((264, 128, 64), (264, 128, 64), (0.8, 1.2), np.float32),   # > 2048 tiles: strided WGs
     ((120, 100, 80), (30, 25, 20), (3.5, 4.0), np.int16),       # footprints beyond LDS
     ((40, 36, 30), (70, 60, 52), (0.45, 0.55), np.float32),     # upsampling, tiny footprints
+    ((30, 28, 24), (96, 90, 80), (0.28, 0.32), np.float32),     # > 2^7 samples per cell: 64-bit sums
 ])
 def test_affine_backward_tiles_and_footprints(in_dim, out_dim, scale, dtype):
     """Image and parameter adjoints across persistent tile striding, tiles
@@ -1238,6 +1239,62 @@ def test_batched_backward_tile_counts_around_xcd_chunks(tiles):
         r_img, r_M, _ = oracle.warp_backward(img, M, g)
         assert_grad(_np(gis[k]), r_img, f"job {k} g_img vs oracle")
         assert_grad(_np(gMs[k]), r_M, f"job {k} g_M vs oracle")
+
+
+@pytest.mark.parametrize("scale", [0.5, 0.3])
+def test_affine_backward_same_sign_gradients_fill_the_fixed_point_range(scale):
+    """A constant upstream gradient (every contribution of a cell the same
+    sign) under upsampling, where the most samples share an input cell: at
+    scale 0.5 the bound admits the 32-bit tile sums at their largest count
+    (2^7), at 0.3 it does not (64-bit sums).  No rotation, so the samples
+    fall on the bound's lattice; single call and batch against the oracle."""
+    in_dim, out_dim = (30, 26, 22), (56, 48, 40)
+    img, _ = phantom_pair(in_dim, seed=61)
+    img = img.astype(np.float32)
+    prm = identity_affine_params()
+    prm[3:6] = scale
+    prm[21:24] = [0.25, -0.5, 0.125]
+    _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+    assert abs(M[0] - scale) < 1e-6 and M[1] == 0 and M[2] == 0
+    g = np.full(out_dim, 0.99, np.float32)
+    r_img, r_M, _ = oracle.warp_backward(img, M, g)
+    g_img, g_M = ctaug.warp_affine_backward(_t(img), M, _t(g))
+    assert_grad(_np(g_img), r_img, "g_img")
+    assert_grad(_np(g_M), r_M, "g_M")
+    gi = torch.zeros(in_dim, dtype=torch.float32, device=DEV)
+    gM = torch.empty(12, dtype=torch.float64, device=DEV)
+    ctaug.ops.warp_affine_backward_batch([ctaug.ops.make_bwd_job(_t(img), M, _t(g), grad_img=gi,
+                                                                 grad_M=gM)])
+    assert_grad(_np(gi), r_img, "batched g_img")
+    assert_grad(_np(gM), r_M, "batched g_M")
+
+
+def test_batched_backward_mixes_32_and_64_bit_jobs():
+    """A batch of jobs whose sample bound admits 32-bit tile sums and one
+    strongly upsampling job that does not (the whole launch takes 64-bit
+    sums): every job against the oracle and the single call."""
+    rng = np.random.default_rng(77)
+    items = []
+    for k, sc in enumerate([(0.9, 1.1), (0.28, 0.3), (0.8, 1.2)]):
+        in_dim = (26, 24, 30)
+        out_dim = (40, 36, 48) if sc[0] < 0.5 else (24, 26, 28)
+        img, _ = phantom_pair(in_dim, seed=90 + k)
+        img = img.astype(np.float32)
+        prm = draw_affine_params(rng, AugmentRanges(scale=sc), in_dim, out_dim)
+        _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+        g = rng.standard_normal(out_dim).astype(np.float32)
+        items.append((img, M, g))
+    gis = [torch.zeros(it[0].shape, dtype=torch.float32, device=DEV) for it in items]
+    gMs = [torch.empty(12, dtype=torch.float64, device=DEV) for _ in items]
+    ctaug.ops.warp_affine_backward_batch([
+        ctaug.ops.make_bwd_job(_t(img), M, _t(g), grad_img=gi, grad_M=gM)
+        for (img, M, g), gi, gM in zip(items, gis, gMs)])
+    for k, (img, M, g) in enumerate(items):
+        r_img, r_M, _ = oracle.warp_backward(img, M, g)
+        assert_grad(_np(gis[k]), r_img, f"job {k} g_img vs oracle")
+        assert_grad(_np(gMs[k]), r_M, f"job {k} g_M vs oracle")
+        s_img, s_M = ctaug.warp_affine_backward(_t(img), M, _t(g))
+        assert_grad(_np(gis[k]), _np(s_img).astype(np.float64), f"job {k} g_img vs single")
 
 
 @pytest.mark.parametrize("dtype,n", [(np.float32, 10), (np.int16, 3)])
