@@ -279,16 +279,37 @@ __device__ __forceinline__ void write_partial_row(const double (&acc)[12],
     __syncthreads();                   // red is reused by the next row
 }
 
+// The upstream gradient of the calling thread's run in tile t of job J
+// (voxels z0 + zr + 4k of row (x0 + xr, y0 + yr)); 0 past the output.
+__device__ __forceinline__ void load_run_g(const FwdJob &J, const float *__restrict__ g, int t,
+                                           int zr, int yr, int xr, float (&gv)[4])
+{
+    const Tiling TL = kBwdTiling;
+    const int tz = t % J.tiles_z, rest = t / J.tiles_z;
+    const int ty = rest % J.tiles_y, tx = rest / J.tiles_y;
+    const int x = (tx << TL.lx) + xr, y = (ty << TL.ly) + yr, z = (tz << TL.lz) + zr;
+    const bool row_ok = x < J.ox && y < J.oy;
+    const int32_t v0 = row_ok ? (x * J.oy + y) * J.oz + z : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        gv[k] = row_ok && z + 4 * k < J.oz ? g[v0 + 4 * k] : 0.0f;
+}
+
 // The adjoint of one 8 x 8 x 16 output tile t of job J, for the calling
 // thread's run (voxels z0 + zr + 4k of row (xr, yr)): coordinates, the
 // staged footprint, dV/dq and its FP64 parameter sums (into acc), the image
 // adjoint (fixed-point tile sums, flushed with FP32 atomics), the
-// displacement gradient and the control-grid contraction.  Uniform over the
-// workgroup; ends with every LDS read and write of the tile done.
+// displacement gradient and the control-grid contraction.  gin holds the
+// run's upstream gradient (load_run_g); the next tile's (tn of job Jn, when
+// has_next) is loaded into gnext once the image scatter is done, so that its
+// latency hides behind the flush.  Uniform over the workgroup; ends with
+// every LDS read and write of the tile done.
 template <typename T, int DISP, bool NARROW>
 __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                                          gconst<float> *disp, int32_t nvox, bool empty_in,
-                                         bool want_ctrl, bool need_dv, const float *__restrict__ g,
+                                         bool want_ctrl, bool need_dv, const float (&gin)[4],
+                                         bool has_next, const FwdJob &Jn,
+                                         const float *__restrict__ gn, int tn, float (&gnext)[4],
                                          float *__restrict__ g_img, float *__restrict__ g_disp,
                                          float *s_ctrl, int32_t lds_cells, int fix_bits, int zr,
                                          int yr, int xr, double (&acc)[12], int (*s_red)[6],
@@ -302,6 +323,7 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
               z1 = min(z0 + (1 << TL.lz), J.oz) - 1;
     const int x = x0 + xr, y = y0 + yr, z = z0 + zr;
     const bool run_ok = x <= x1 && y <= y1 && z <= z1;
+    bool fetched = false;              // gnext loaded (uniform)
     const int nvalid = run_ok ? min(4, (z1 - z) / 4 + 1) : 0;
     const int32_t v0 = run_ok ? (x * J.oy + y) * J.oz + z : 0;
     // coordinates, guard and upstream gradient of the run's voxels
@@ -342,7 +364,7 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
             // adjoint of the photometric chain without window: the output
             // is gain * V + offset + sigma * n off the occluded slab and
             // does not depend on V on it
-            float gv = g[v];
+            float gv = gin[k];
             if (J.flags & kFlagPhoto) {
                 gv = J.gain * gv;
                 if ((J.flags & kFlagOcclude) && zf >= J.occ_lo && zf <= J.occ_hi)
@@ -541,6 +563,10 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                     __builtin_amdgcn_sched_barrier(0);       // one voxel at a time
                 }
                 __syncthreads();
+                if (has_next && !fetched) {
+                    load_run_g(Jn, gn, tn, zr, yr, xr, gnext);
+                    fetched = true;
+                }
                 // flush: one global atomic per touched in-volume footprint cell
                 for (int c = threadIdx.x; c < n; c += kThreads) {
                     const int v = s_acc[c];
@@ -639,6 +665,14 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
             }
         }
     }
+    if (!fetched) {
+        if (has_next)
+            load_run_g(Jn, gn, tn, zr, yr, xr, gnext);
+        else
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                gnext[k] = 0.0f;
+    }
 }
 
 // Register budgets follow the LDS: a displacement takes the whole 48 KB
@@ -692,12 +726,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int yr = (threadIdx.x >> 2) & 7;
     const int xr = threadIdx.x >> 5;
 
-    for (XcdSlots slots(b >> 3, per_xcd_wg);; slots.next()) {
-        const int t = xcd_tile(b & 7, slots.slot());
-        if (t >= ntiles)
-            break;
-        bwd_tile<T, DISP, NARROW>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, g, g_img, g_disp,
-                          s_ctrl, lds_cells, fix_bits, zr, yr, xr, acc, s_red, s_gmax);
+    XcdSlots slots(b >> 3, per_xcd_wg);
+    int t = xcd_tile(b & 7, slots.slot());
+    float gcur[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (t < ntiles)
+        load_run_g(J, g, t, zr, yr, xr, gcur);
+    while (t < ntiles) {
+        slots.next();
+        const int tn = xcd_tile(b & 7, slots.slot());
+        float gnext[4];
+        // affine: the next tile's gradient is loaded during this tile's flush;
+        // a displacement's tiles load their own at the start
+        bwd_tile<T, DISP, NARROW>(J, t, src, disp, nvox, empty_in, want_ctrl, need_dv, gcur,
+                                  DISP == kDispNone && tn < ntiles, J, g, tn, gnext, g_img, g_disp,
+                                  s_ctrl, lds_cells, fix_bits, zr, yr, xr, acc, s_red, s_gmax);
+        if (DISP != kDispNone && tn < ntiles)
+            load_run_g(J, g, tn, zr, yr, xr, gnext);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            gcur[k] = gnext[k];
+        t = tn;
     }
 
     if (want_ctrl)                         // the last tile ended with a barrier
@@ -717,7 +765,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 // increasing order (xcd_tile), so the jobs a workgroup meets come in
 // increasing order.  The
 // workgroup's FP64 parameter sums of job j go to partials row
-// j * gridDim.x + b (rows of jobs it never meets stay as zeroed before).
+// j * gridDim.x + b; it writes zeros to the rows of the jobs it never meets
+// (no zeroing launch before).
 template <typename T, bool NARROW>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_warp_bwd_batch(const BwdBatch B,
                                                              double *__restrict__ partials,
@@ -736,33 +785,57 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
-    int jcur = -1;
-    for (XcdSlots slots(b >> 3, per_xcd_wg);; slots.next()) {
-        const int t = xcd_tile(b & 7, slots.slot());
-        if (t >= total)
-            break;
-        int j = 0;                     // the job holding tile t (uniform)
+    // rows of jobs jlo .. jhi - 1, which this workgroup does not meet: zeros
+    auto zero_rows = [&](int jlo, int jhi) {
+        for (int e = threadIdx.x; e < (jhi - jlo) * 12; e += kThreads)
+            partials[((int64_t)(jlo + e / 12) * gridDim.x + b) * 12 + e % 12] = 0.0;
+    };
+    auto job_of = [&](int t) {         // the job holding tile t (uniform)
+        int j = 0;
         for (int i = 1; i < B.njobs; ++i)
             j += B.prefix[i] <= t;
-        if (j != jcur) {               // the whole workgroup switches jobs
+        return j;
+    };
+    int jcur = -1;
+    XcdSlots slots(b >> 3, per_xcd_wg);
+    int t = xcd_tile(b & 7, slots.slot());
+    int j = t < total ? job_of(t) : 0;
+    float gcur[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (t < total)
+        load_run_g(B.jobs[j].J, B.jobs[j].g, t - B.prefix[j], zr, yr, xr, gcur);
+    while (t < total) {
+        if (j != jcur) {               // the whole workgroup switches jobs (j > jcur)
             if (jcur >= 0 && B.jobs[jcur].g_M) {
                 write_partial_row(acc, red, partials + ((int64_t)jcur * gridDim.x + b) * 12);
 #pragma unroll
                 for (int i = 0; i < 12; ++i)
                     acc[i] = 0.0;
             }
+            zero_rows(jcur + 1, j);
             jcur = j;
         }
+        slots.next();
+        const int tn = xcd_tile(b & 7, slots.slot());
+        const int jn = tn < total ? job_of(tn) : j;
         const BwdJob &BJ = B.jobs[j];
+        const BwdJob &BN = B.jobs[jn];
         const Src src = make_src<T>(BJ.J);
         const bool empty_in = BJ.J.nx == 0 || BJ.J.ny == 0 || BJ.J.nz == 0;
-        bwd_tile<T, kDispNone, NARROW>(BJ.J, t - B.prefix[j], src, nullptr, BJ.J.ox * BJ.J.oy * BJ.J.oz,
-                               empty_in, false, BJ.g_M != nullptr, BJ.g, BJ.g_img, nullptr,
-                               nullptr, lds_cells, B.fix_bits[j], zr, yr, xr, acc, s_red,
-                               s_gmax);
+        float gnext[4];
+        bwd_tile<T, kDispNone, NARROW>(BJ.J, t - B.prefix[j], src, nullptr,
+                                       BJ.J.ox * BJ.J.oy * BJ.J.oz, empty_in, false,
+                                       BJ.g_M != nullptr, gcur, tn < total, BN.J, BN.g,
+                                       tn - B.prefix[jn], gnext, BJ.g_img, nullptr, nullptr,
+                                       lds_cells, B.fix_bits[j], zr, yr, xr, acc, s_red, s_gmax);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            gcur[k] = gnext[k];
+        t = tn;
+        j = jn;
     }
     if (jcur >= 0 && B.jobs[jcur].g_M)
         write_partial_row(acc, red, partials + ((int64_t)jcur * gridDim.x + b) * 12);
+    zero_rows(jcur + 1, B.njobs);
 }
 
 // grad_M of job blockIdx.x: its rows j * nrows .. (j + 1) * nrows - 1 summed
@@ -1090,9 +1163,10 @@ hipError_t launch_warp_bwd(const FwdJob &J0, const float *g, float *g_img, float
 }
 
 // Batched affine adjoint: chunks of up to kBwdBatchMax jobs, each one
-// persistent launch (its job table in the kernel arguments), a zeroing of
-// its partial rows and one reduction launch.  partials: kBwdMaxRows * 12
-// doubles per job.
+// persistent launch (its job table in the kernel arguments; every workgroup
+// writes its partial row of every job, zeros where it met none of the job's
+// tiles) and one reduction launch; a chunk with no tiles zeroes its rows in
+// a launch of its own.  partials: kBwdMaxRows * 12 doubles per job.
 hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials, hipStream_t s)
 {
     for (int32_t c0 = 0; c0 < n; c0 += kBwdBatchMax) {
@@ -1128,7 +1202,7 @@ hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials
                 : (narrow ? &k_warp_bwd_batch<float, true> : &k_warp_bwd_batch<float, false>);
         const int grid =
             total > 0 ? bwd_launch_grid(reinterpret_cast<const void *>(kern), lds, total) : 8;
-        if (any_M) {
+        if (any_M && total == 0) {     // else the kernel writes every row
             const int64_t nz = (int64_t)B.njobs * grid * 12;
             hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((nz + kThreads - 1) / kThreads)),
                                dim3(kThreads), 0, s, part, nz);

@@ -1297,6 +1297,43 @@ def test_batched_backward_mixes_32_and_64_bit_jobs():
         assert_grad(_np(gis[k]), _np(s_img).astype(np.float64), f"job {k} g_img vs single")
 
 
+def test_batched_backward_writes_every_partial_row():
+    """Jobs with no tiles (an empty output) before, between and after jobs
+    with tiles, then a batch of empty jobs only, each over a workspace
+    filled with NaN bytes first: every grad_M against the oracle (zeros for
+    the empty jobs), as every workgroup writes its row of every job."""
+    rng = np.random.default_rng(404)
+    need = ctaug.ops.warp_affine_backward_batch_workspace(5)
+    ws = torch.full((need,), 255, dtype=torch.uint8, device=DEV)
+    specs = [((20, 22, 24), (0, 20, 22)), ((20, 22, 24), (18, 20, 22)),
+             ((18, 16, 20), (9, 0, 5)), ((16, 18, 20), (17, 15, 33)),
+             ((12, 14, 16), (6, 7, 0))]
+    items = []
+    for k, (in_dim, out_dim) in enumerate(specs):
+        img, _ = phantom_pair(in_dim, seed=500 + k)
+        img = img.astype(np.float32)
+        prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+        _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+        g = rng.standard_normal(out_dim).astype(np.float32)
+        items.append((img, M, g))
+    for batch in ([0, 1, 2, 3, 4], [0, 2, 4]):
+        ws.fill_(255)
+        gis = {k: torch.zeros(items[k][0].shape, dtype=torch.float32, device=DEV) for k in batch}
+        gMs = {k: torch.full((12,), np.nan, dtype=torch.float64, device=DEV) for k in batch}
+        ctaug.ops.warp_affine_backward_batch(
+            [ctaug.ops.make_bwd_job(_t(items[k][0]), items[k][1], _t(items[k][2]),
+                                    grad_img=gis[k], grad_M=gMs[k]) for k in batch], ws)
+        for k in batch:
+            img, M, g = items[k]
+            r_img, r_M, _ = oracle.warp_backward(img, M, g)
+            if g.size == 0:
+                assert np.array_equal(_np(gMs[k]), np.zeros(12)), (batch, k)
+                assert not _np(gis[k]).any(), (batch, k)
+            else:
+                assert_grad(_np(gMs[k]), r_M, f"{batch} job {k} g_M")
+                assert_grad(_np(gis[k]), r_img, f"{batch} job {k} g_img")
+
+
 @pytest.mark.parametrize("dtype,n", [(np.float32, 10), (np.int16, 3)])
 def test_batched_backward_matches_single_calls_and_oracle(dtype, n):
     """One batched adjoint launch (two for ten jobs) over volumes of uneven
