@@ -514,10 +514,12 @@ def test_affine_backward_parity(dims, dtype):
 @pytest.mark.parametrize("gscale,outliers", [(1e30, 0.0), (1e-30, 0.0), (1.0, 1e-12),
                                              (1e-36, 0.0)])
 def test_affine_backward_gradient_magnitudes(gscale, outliers):
-    """The image adjoint sums a tile in 64-bit fixed point scaled by the tile's
-    largest |g|: huge gradients, tiny ones (down to FP32 subnormal products),
-    and a few normal values among 1e-12 ones (rounded at 2^-51 of the tile
-    maximum), against the oracle."""
+    """The image adjoint sums a tile in fixed point scaled by the tile's
+    largest |g| (32-bit here, as the map bounds a cell's samples; a tile
+    maximum below 2^-96 takes per-corner FP32 atomics): huge gradients, tiny
+    ones (down to FP32 subnormal products), and a few normal values among
+    1e-12 ones (rounded within 2^(b - 30) of the tile maximum), against the
+    oracle."""
     rng = np.random.default_rng(int(abs(np.log10(gscale))) + 3)
     dims = (40, 36, 44)
     img, _ = phantom_pair(dims, seed=25)
