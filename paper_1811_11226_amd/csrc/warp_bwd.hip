@@ -786,9 +786,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int i = 0; i < 12; ++i)
         acc[i] = 0.0;
     // rows of jobs jlo .. jhi - 1, which this workgroup does not meet: zeros
+    // (only jobs with grad_M have rows: without any, partials may be null)
     auto zero_rows = [&](int jlo, int jhi) {
-        for (int e = threadIdx.x; e < (jhi - jlo) * 12; e += kThreads)
-            partials[((int64_t)(jlo + e / 12) * gridDim.x + b) * 12 + e % 12] = 0.0;
+        for (int e = threadIdx.x; e < (jhi - jlo) * 12; e += kThreads) {
+            const int jj = jlo + e / 12;
+            if (B.jobs[jj].g_M)
+                partials[((int64_t)jj * gridDim.x + b) * 12 + e % 12] = 0.0;
+        }
     };
     auto job_of = [&](int t) {         // the job holding tile t (uniform)
         int j = 0;
@@ -1190,7 +1194,7 @@ hipError_t launch_warp_bwd_batch(const BwdJob *jobs, int32_t n, double *partials
             any_M = any_M || B.jobs[i].g_M;
         }
         B.prefix[B.njobs] = (int32_t)total;
-        double *part = partials + (int64_t)c0 * kBwdMaxRows * 12;
+        double *part = partials ? partials + (int64_t)c0 * kBwdMaxRows * 12 : nullptr;
         const bool i16 = B.jobs[0].J.dtype == kI16;
         const size_t lds = (size_t)cells * sizeof(float);
         bool narrow = true;            // the 32-bit image adjoint when every job has a bound

@@ -1299,6 +1299,32 @@ def test_batched_backward_mixes_32_and_64_bit_jobs():
         assert_grad(_np(gis[k]), _np(s_img).astype(np.float64), f"job {k} g_img vs single")
 
 
+def test_batched_backward_image_only_without_workspace():
+    """No job wants grad_M, so the C call takes no workspace (NULL): grad_img
+    of every job (ten, two launches) against the oracle."""
+    rng = np.random.default_rng(606)
+    items, jobs, gis = [], [], []
+    for k in range(10):
+        in_dim = tuple(int(v) for v in rng.integers(12, 30, 3))
+        out_dim = tuple(int(v) for v in rng.integers(10, 34, 3))
+        img, _ = phantom_pair(in_dim, seed=620 + k)
+        img = img.astype(np.float32)
+        prm = draw_affine_params(rng, AugmentRanges(), in_dim, out_dim)
+        _, M = ctaug.affine_matrix(prm, in_dim, out_dim)
+        g = rng.standard_normal(out_dim).astype(np.float32)
+        gi = torch.zeros(in_dim, dtype=torch.float32, device=DEV)
+        items.append((img, M, g))
+        gis.append(gi)
+        jobs.append(ctaug.ops.make_bwd_job(_t(img), M, _t(g), grad_img=gi, grad_M=None))
+    arr = (ctaug._lib.BwdJob * len(jobs))(*jobs)
+    L = ctaug._lib.load()
+    assert L.ctaug_warp_affine_backward_batch(arr, len(jobs), None, 0, ctaug.ops._stream()) == 0
+    torch.cuda.synchronize()
+    for k, (img, M, g) in enumerate(items):
+        r_img, _, _ = oracle.warp_backward(img, M, g)
+        assert_grad(_np(gis[k]), r_img, f"job {k} g_img")
+
+
 def test_batched_backward_writes_every_partial_row():
     """Jobs with no tiles (an empty output) before, between and after jobs
     with tiles, then a batch of empty jobs only, each over a workspace
