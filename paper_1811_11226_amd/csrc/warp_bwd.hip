@@ -123,15 +123,13 @@ __device__ __forceinline__ long long to_fixed(float v, double S)
 // accumulators take the cells the staged image took).  The host bounds how
 // many of a tile's samples can have one input cell among their corners: at
 // most 2^b (fixed32_bits).  Each contribution is scaled by 2^sc, sc = 30 - b
-// - e (v_ldexp, exact), and rounded to the nearest integer: |v 2^sc| <
-// 2^(30 - b), so a cell's sum of at most 2^b of them stays within 2^30.  The
-// unit 2^-sc is at most 2^(b - 29) gmax, so for b <= kFixed32MaxBits the
-// rounding stays within 2^-23 gmax, the order of the FP32 product's own.
+// - e (exact: the voxel's gradient is multiplied by the power of two before
+// the weights, which rounds as the unscaled product would), and rounded to
+// the nearest integer: |v 2^sc| < 2^(30 - b), so a cell's sum of at most 2^b
+// of them stays within 2^30.  The unit 2^-sc is at most 2^(b - 29) gmax, so
+// for b <= kFixed32MaxBits the rounding stays within 2^-23 gmax, the order
+// of the FP32 product's own.
 constexpr int kFixed32MaxBits = 7;
-__device__ __forceinline__ int to_fixed32(float v, int sc)
-{
-    return (int)__builtin_rintf(__builtin_ldexpf(v, sc));
-}
 
 // Spline weight matrix of one tile axis: Wt[p][c] = B_{c - (i(p) - i(p0))}(t(p))
 // for the 2^lp voxels p0 + p <= p1 of the axis and the window of kSplineWindow
@@ -539,6 +537,7 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                 // one pass, 32-bit accumulators (gmax >= 2^-96 keeps every
                 // scaled value and every flushed sum in the normal range)
                 const int sc = 30 - fix_bits - (ilogbf(gm) + 1);
+                const float S32 = __builtin_ldexpf(1.0f, sc);    // normal: sc in [-105, 125]
                 int *s_acc = reinterpret_cast<int *>(s_cells);
                 const int n = G.e[0] * sxy;                      // a multiple of 4
                 for (int c = 4 * threadIdx.x; c < n; c += 4 * kThreads)
@@ -550,15 +549,16 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                         continue;
                     const float wx[2] = {1.0f - tw[k][0], tw[k][0]};
                     const float wy[2] = {1.0f - tw[k][1], tw[k][1]};
-                    const float gz0 = (1.0f - tw[k][2]) * gk[k], gz1 = tw[k][2] * gk[k];
+                    const float gks = gk[k] * S32;
+                    const float gz0 = (1.0f - tw[k][2]) * gks, gz1 = tw[k][2] * gks;
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
                         for (int bb = 0; bb < 2; ++bb) {
                             const float wxy = wx[a] * wy[bb];
                             int *row = s_acc + base[k] + a * sxy + bb * pitch;
-                            atomicAdd(row, to_fixed32(wxy * gz0, sc));
-                            atomicAdd(row + 1, to_fixed32(wxy * gz1, sc));
+                            atomicAdd(row, (int)__builtin_rintf(wxy * gz0));
+                            atomicAdd(row + 1, (int)__builtin_rintf(wxy * gz1));
                         }
                     __builtin_amdgcn_sched_barrier(0);       // one voxel at a time
                 }
@@ -1005,7 +1005,7 @@ bool bwd_ctrl_fused(const BsplineGeom &B)
 }
 
 // Exponent b of the 32-bit fixed-point image adjoint of an affine job (see
-// to_fixed32), or -1 for the 64-bit one.  Sample p reaches input cell c when
+// kFixed32MaxBits), or -1 for the 64-bit one.  Sample p reaches input cell c when
 // q(p) = A p + t lies in [c - 1, c + 1) per axis, widened by the bound delta
 // on q's FP32 rounding; those p lie in A^-1 of that cube, whose extent along
 // output axis i is w_i = (2 + 2 delta) sum_j |A^-1_ij|, which holds at most
