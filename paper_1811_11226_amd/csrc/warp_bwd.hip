@@ -524,12 +524,12 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
         if (g_img) {
             // the tile's largest |g| (the waves' maxima, written before the
             // barrier that ended the corner reads); every wave reads it before
-            // any wave goes on to the next tile, which writes s_gmax again
+            // any wave goes on to the next tile, which writes s_gmax again:
+            // each branch below passes a barrier before the tile ends
             float gm = s_gmax[0];
 #pragma unroll
             for (int w = 1; w < kThreads / 64; ++w)
                 gm = fmaxf(gm, s_gmax[w]);
-            __syncthreads();
             // x-planes of 64-bit accumulators that fit the footprint reservation
             const int planes = (lds_cells >> 1) / sxy;
             const float rcp_pitch = 1.0f / (float)pitch, rcp_ey = 1.0f / (float)ey;
@@ -637,13 +637,14 @@ __device__ __forceinline__ void bwd_tile(const FwdJob &J, int t, const Src &src,
                     }
                     __syncthreads();   // LDS is reused next
                 }
-            } else if (gm != 0.0f) {
+            } else {
+                __syncthreads();       // every wave has read s_gmax
                 // non-finite gradients, a footprint too large for one x-plane
                 // of 64-bit accumulators, or a 32-bit tile with gmax < 2^-96:
-                // FP32 global atomics per corner
+                // FP32 global atomics per corner (none when gmax = 0)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (!live[k])
+                    if (!live[k] || gm == 0.0f)
                         continue;
                     const int rel = base[k] - cx0[k] * sxy;
                     const int cy0 = rel / pitch, cz0 = rel - cy0 * pitch;
